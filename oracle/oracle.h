@@ -1,0 +1,100 @@
+/*
+ * FP64 reference ("oracle") for the ray-cast colouring and filtering path of
+ * Vohl, Fluke, Barnes & Hassan (2017), "Real-time colouring and filtering with
+ * graphics shaders".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, header or constant
+ * with the HIP library and is deliberately plain and slow: one ray at a time, no
+ * bricking, no fusion, every step in double precision in the order the paper gives.
+ *
+ * Cube layout: C-order [z][y][x], x fastest (x = RA, y = Dec, z = velocity).
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Appendix A: parallel (type 0) or perspective (type 1) projection. */
+typedef struct {
+    int32_t type;
+    double eye[3], U[3], V[3], W[3];
+    int32_t width, height;
+} orc_camera;
+
+/* Transfer functions of Section 3 (Alg. MIP0, AVIP0, MIP1, AVIP1, MIP_RGB, AVIP_RGB). */
+enum { ORC_MIP0 = 0, ORC_MIP1 = 1, ORC_MIPRGB = 2, ORC_AVIP0 = 3, ORC_AVIP1 = 4, ORC_AVIPRGB = 5 };
+/* Section 4 filters: none, intensity clipping, intensity domain scaling. */
+enum { ORC_FILTER_NONE = 0, ORC_FILTER_CLIP = 1, ORC_FILTER_SCALE = 2 };
+
+typedef struct {
+    int32_t mode;             /* ORC_MIP0 .. ORC_AVIPRGB */
+    int32_t filter;           /* ORC_FILTER_* */
+    int32_t box_arm;          /* Section 4.1 filterArm (0 = no box smoothing) */
+    int32_t mip_alpha;        /* 0: table alpha / s_max, 1: opaque, 2: transparent only at or below minT */
+    int32_t ratio;            /* 0 none, 1 line ratio method 1, 2 method 2 (Section 4.5) */
+    int32_t opacity_from_lut; /* 0: a = k*s (Alg. AVIP0); 1: a = k*table(s).a */
+    double k, min_val, ert;   /* AVIP weighting factor, minVal, termination threshold (0.99) */
+    double lo, hi;            /* colour-map domain; DATAMIN = lo */
+    double dt;                /* step along the unit ray direction, in voxels */
+    double min_t, max_t;      /* thresholds (cube 1 for the ratio methods) */
+    double min_t2, max_t2;    /* thresholds for cube 2 (ratio methods) */
+    double ratio_lo, ratio_hi;/* domain the ratio is normalised over */
+} orc_params;
+
+/* Margins below which a discrete decision counts as "could flip" (fragile pixel). */
+typedef struct {
+    double ds;  /* MIP argmax: gap between the maximum and another sample (s units) */
+    double dv;  /* threshold tests on raw values: |v - threshold| */
+    double da;  /* early termination: |alpha - ert| */
+    double dn;  /* sample count: distance of L/dt from an integer, relative */
+    double dr;  /* ratio denominators: |v1| below this makes the ratio ill-conditioned */
+} orc_margins;
+
+/* Render npix pixels (pix == NULL: all width*height pixels, row-major).  V2 is the second
+ * cube for the ratio methods (NULL otherwise).  lut: M RGBA entries at j/(M-1).
+ * Outputs rgba[4*npix], fragile[npix] (0/1), nsamples[npix] (may be NULL).
+ * Returns 0 on success, nonzero on invalid arguments. */
+int orc_render(const double* V, const double* V2, int32_t nx, int32_t ny, int32_t nz,
+               const orc_camera* cam, const double* lut, int32_t M, const orc_params* p,
+               const orc_margins* mg, int64_t npix, const int64_t* pix,
+               double* rgba, uint8_t* fragile, int32_t* nsamples, int32_t nthreads);
+
+/* Ray of pixel (px, py): origin o and unit direction d.  Entry/exit of the cell-centred
+ * box [-0.5, n-0.5]^3.  Returns 1 and t0 < t1 when the ray (t >= 0) meets the box. */
+void orc_pixel_ray(const orc_camera* cam, int32_t px, int32_t py, double o[3], double d[3]);
+int orc_ray_box(int32_t nx, int32_t ny, int32_t nz, const double o[3], const double d[3],
+                double* t0, double* t1);
+/* Trilinear sample with clamp-to-edge at point p (voxel centres at integers). */
+double orc_trilinear(const double* V, int32_t nx, int32_t ny, int32_t nz, const double p[3]);
+
+/* AVIP0 with a piecewise-linear RGBA transfer function (colour = tf(s).rgb, opacity =
+ * k * tf(s).a), and its reverse-mode derivative, storing every sample.  grad_rgba holds
+ * dL/dRGBA for the npix pixels; grad_tf[M*4] and grad_vox[nx*ny*nz] are ACCUMULATED
+ * (caller zeroes them).  Single-threaded, deterministic. */
+int orc_render_grad(const double* V, int32_t nx, int32_t ny, int32_t nz,
+                    const orc_camera* cam, const double* tf, int32_t M, const orc_params* p,
+                    int64_t npix, const int64_t* pix, const double* grad_rgba,
+                    double* rgba, double* grad_tf, double* grad_vox);
+
+/* Separable 3D smoothing with clamp-to-edge: out = (g x g x g) applied along x, then y,
+ * then z.  taps g[0..T-1], T odd, centred.  tmp: scratch of nx*ny*nz doubles. */
+int orc_smooth(const double* V, int32_t nx, int32_t ny, int32_t nz, const double* g,
+               int32_t T, double* out, double* tmp, int32_t nthreads);
+/* Same operator evaluated at selected voxels by the direct triple sum. */
+int orc_smooth_at(const double* V, int32_t nx, int32_t ny, int32_t nz, const double* g,
+                  int32_t T, int64_t npts, const int64_t* idx, double* out);
+
+/* Voxel-wise line ratio of two equal-length spectral windows of one cube. */
+int orc_line_ratio(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t z0a,
+                   int32_t z0b, int32_t nzw, double min_t_a, double min_t_b, double datamin,
+                   double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

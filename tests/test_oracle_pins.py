@@ -1,0 +1,559 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix (CPU only).
+
+Each test names the passage it pins.  None of them re-types the oracle's own recurrence:
+they use closed forms, library routines (scipy's trilinear interpolation and 1D
+correlation, numpy's binary16 cast, torch's bfloat16 cast), invariants and brute force.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+from oracle import taps, quant
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def scipy_trilinear(cube, pts):
+    """Library trilinear interpolation, clamp-to-edge, at points (N, 3) given as (x, y, z)."""
+    coords = np.stack([pts[:, 2], pts[:, 1], pts[:, 0]])  # order [z][y][x]
+    return ndimage.map_coordinates(np.asarray(cube, np.float64), coords, order=1,
+                                   mode="nearest")
+
+
+def norm01(v, lo, hi):
+    return np.clip((v - lo) / (hi - lo), 0.0, 1.0)
+
+
+def ortho_z_samples(n, width, height, dt=0.5):
+    """Sample positions of an axis-aligned parallel projection along +z through an n^3
+    cube whose image spans one face (closed form: z = -0.5 + k dt, k < n/dt)."""
+    px, py = np.meshgrid(np.arange(width), np.arange(height), indexing="xy")
+    x = (n - 1) / 2.0 + (2.0 * (px + 0.5) / width - 1.0) * n / 2.0
+    y = (n - 1) / 2.0 + (2.0 * (py + 0.5) / height - 1.0) * n / 2.0
+    zs = -0.5 + dt * np.arange(int(round(n / dt)))
+    return x.ravel(), y.ravel(), zs
+
+
+# ------------------------------------------------------------------ trilinear, ray/box
+def test_trilinear_matches_library_interpolation():
+    """The fetch cube[loc] (Alg. 1) is trilinear with clamp-to-edge: equal to scipy's
+    order-1 map_coordinates with mode 'nearest' at random points, in and outside."""
+    rng = np.random.default_rng(3)
+    cube = rng.standard_normal((7, 9, 11))
+    pts = rng.uniform(-2.0, 13.0, size=(500, 3))
+    ref = scipy_trilinear(cube, pts)
+    got = np.array([oracle.trilinear(cube, p) for p in pts])
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_ray_box_entry_on_surface_and_chord_by_bruteforce():
+    """Appendix A rays against the cell-centred box [-0.5, n-0.5]^3: the entry point lies
+    on the box surface and the chord length agrees with dense brute-force sampling."""
+    rng = np.random.default_rng(5)
+    n = (6, 9, 13)  # (nz, ny, nx)
+    hi = np.array([n[2], n[1], n[0]]) - 0.5
+    hits = 0
+    for _ in range(200):
+        o = rng.uniform(-15, 25, 3)
+        target = rng.uniform(-1.0, 1.0, 3) * (hi + 1.0)
+        d = (target - o) if rng.random() < 0.75 else rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        r = oracle.ray_box(n, o, d)
+        ts = np.linspace(0, 60, 600001)
+        pts = o[None] + ts[:, None] * d[None]
+        inside = np.all((pts >= -0.5) & (pts <= hi[None]), axis=1)
+        if r is None:
+            assert inside.sum() <= 1
+            continue
+        hits += 1
+        t0, t1 = r
+        assert abs((t1 - t0) - inside.sum() * 1e-4) < 3e-4
+        p0 = o + t0 * d
+        if t0 > 0:
+            on_face = np.isclose(p0, -0.5, atol=1e-9) | np.isclose(p0, hi, atol=1e-9)
+            assert on_face.any()
+    assert hits > 40
+
+
+# ------------------------------------------------------------------ MIP pins (P2-P4)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mip0_axis_aligned_is_column_max(seed):
+    """Eq. MIP along z with one ray per voxel column (64x64 image on a 64^3 cube): the
+    result is colourMap(max_z V) exactly (trilinear weights are 0/1 or clamp)."""
+    cube = synth.cfg0_cube(seed)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.ortho_axis(64, 64, 64, 64, 64, "+z")
+    lut = synth.lut_heat(256)
+    rgba, frag, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi))
+    assert (ns == 128).all() and not frag.any()
+    s = norm01(cube.astype(np.float64).max(axis=0).ravel(), lo, hi)
+    for ch in range(4):
+        ref = np.interp(s, np.arange(256) / 255.0, lut[:, ch].astype(np.float64))
+        assert np.max(np.abs(rgba[:, ch] - ref)) < 1e-12
+
+
+def test_mip0_oversampled_matches_library_trilinear_max():
+    """256x256 rays over a 64^3 cube: MIP0 equals the max over library-interpolated samples
+    at the closed-form sample positions z = -0.5 + 0.5 k, k = 0..127."""
+    cube = synth.cfg0_cube(0)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.ortho_axis(64, 64, 64, 256, 256, "+z")
+    lut = synth.lut_ramp(256)
+    x, y, zs = ortho_z_samples(64, 256, 256)
+    pix = np.random.default_rng(0).choice(256 * 256, 400, replace=False)
+    rgba, _, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi), pixels=pix)
+    assert (ns == 128).all()
+    for i, p in enumerate(pix):
+        pts = np.stack([np.full_like(zs, x[p]), np.full_like(zs, y[p]), zs], 1)
+        s = norm01(scipy_trilinear(cube, pts).max(), lo, hi)
+        ref = np.interp(s, np.arange(256) / 255.0, lut[:, 0].astype(np.float64))
+        assert abs(rgba[i, 0] - ref) < 1e-12
+
+
+def test_mip1_and_rgb_use_last_argmax_and_loc():
+    """Alg. MIP1 / MIP_RGB: the colour comes from the location of the maximum, the later
+    sample winning ties ('>='); loc = (p + 0.5)/n.  Built with planted exact ties."""
+    rng = np.random.default_rng(11)
+    n = 16
+    cube = rng.uniform(0, 1, (n, n, n)).astype(np.float32)
+    # plant an exact tie of the column maximum at two depths in every column
+    cube[3] = 2.0
+    cube[9] = 2.0
+    lut = synth.lut_heat(64)
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    p = dict(lo=0.0, hi=2.0)
+    m1, f1, _ = oracle.render(cube, cam, lut, dict(p, mode="mip1"))
+    rgb, f2, _ = oracle.render(cube, cam, lut, dict(p, mode="miprgb"))
+    # samples at z = 8.5 and 9.0 both read 2.0?  No: 8.5 interpolates planes 8 and 9.
+    zstar = 9.0  # last sample reaching the maximum is the one at z = 9
+    locz = (zstar + 0.5) / n
+    refc = [np.interp(locz, np.arange(64) / 63.0, lut[:, ch].astype(np.float64)) for ch in range(3)]
+    assert np.allclose(m1[:, :3], np.array(refc)[None], atol=1e-12)
+    assert np.allclose(m1[:, 3], 1.0)
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert np.allclose(rgb[:, 0], locz)
+    assert np.allclose(rgb[:, 1], ((yy + 0.5) / n).ravel())
+    assert np.allclose(rgb[:, 2], ((xx + 0.5) / n).ravel())
+    assert np.allclose(rgb[:, 3], 1.0)
+
+
+def test_mirror_views_give_mirrored_mip0():
+    """Parallel views along +z and -z see the same maxima: the images are mirror images."""
+    cube = synth.cfg0_cube(1)
+    lo, hi = quant.finite_minmax(cube)
+    lut = synth.lut_ramp(256)
+    a = synth.ortho_axis(64, 64, 64, 128, 128, "+z")
+    b = synth.ortho_axis(64, 64, 64, 128, 128, "-z")
+    ra, _, _ = oracle.render(cube, a, lut, dict(mode="mip0", lo=lo, hi=hi))
+    rb, _, _ = oracle.render(cube, b, lut, dict(mode="mip0", lo=lo, hi=hi))
+    # both cameras use U = +x, V = +y: identical pixel grids, same maxima
+    assert np.max(np.abs(ra - rb)) < 1e-12
+
+
+def test_axis_transpose_invariance_perspective():
+    """Swapping the cube's x and y axes and the camera's x and y components (and U with V
+    on a square image) transposes the perspective MIP0 image: pins the per-axis handling of
+    oblique rays in ray generation, box entry and interpolation."""
+    cube = synth.blob_cube(24, 3, seed=4)
+    lo, hi = quant.finite_minmax(cube)
+    lut = synth.lut_heat(256)
+    cam = synth.perspective_lookat(24, 24, 24, 35.0, 25.0, 60.0, 40.0, 48, 48)
+    sw = lambda v: (v[1], v[0], v[2])  # noqa: E731
+    cam_t = synth.Camera(1, sw(cam.eye), sw(cam.V), sw(cam.U), sw(cam.W), 48, 48)
+    cube_t = np.ascontiguousarray(np.swapaxes(cube, 1, 2))
+    a, _, na = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi))
+    b, _, nb = oracle.render(cube_t, cam_t, lut, dict(mode="mip0", lo=lo, hi=hi))
+    a = a.reshape(48, 48, 4)
+    b = b.reshape(48, 48, 4)
+    assert np.max(np.abs(a - np.transpose(b, (1, 0, 2)))) < 1e-9
+    assert (na.reshape(48, 48) == nb.reshape(48, 48).T).all()
+    assert (na > 0).sum() > 1000
+
+
+def test_perspective_samples_match_library_trilinear():
+    """Perspective MIP0 at random pixels equals the maximum of library-interpolated samples
+    along the same ray (points o + (t0 + k dt) d, N = ceil((t1 - t0)/dt))."""
+    cube = synth.blob_cube(20, 2, seed=7)
+    lo, hi = quant.finite_minmax(cube)
+    lut = synth.lut_ramp(256)
+    cam = synth.perspective_lookat(20, 20, 20, 50.0, -30.0, 45.0, 50.0, 40, 30)
+    pix = np.arange(40 * 30)
+    rgba, _, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi, dt=0.37),
+                                pixels=pix)
+    checked = 0
+    for i in pix:
+        o, d = oracle.pixel_ray(cam, int(i % 40), int(i // 40))
+        r = oracle.ray_box(cube.shape, o, d)
+        if r is None:
+            assert ns[i] == 0 and np.all(rgba[i] == 0)
+            continue
+        t0, t1 = r
+        N = int(math.ceil((t1 - t0) / 0.37))
+        assert ns[i] == N
+        ts = t0 + 0.37 * np.arange(N)
+        vals = scipy_trilinear(cube, o[None] + ts[:, None] * d[None])
+        s = norm01(vals.max(), lo, hi)
+        assert abs(rgba[i, 0] - s) < 1e-7  # ramp table stored in float32
+        checked += 1
+    assert checked > 300
+
+
+# ------------------------------------------------------------------ AVIP pins (P1, P5, P13)
+def test_avip_uniform_cube_closed_form():
+    """Alg. AVIP0 on a uniform cube with a = k s constant: alpha_n = 1 - (1 - a)^n and the
+    colour is the table colour exactly.  a = 0.01 over 128 samples gives 0.7237483323."""
+    n = 64
+    cube = np.full((n, n, n), 0.5, np.float32)
+    cam = synth.ortho_axis(n, n, n, 8, 8, "+z")
+    lut = synth.lut_heat(256)
+    rgba, frag, ns = oracle.render(cube, cam, lut, dict(mode="avip0", lo=0.0, hi=1.0, k=0.02))
+    assert (ns == 128).all()
+    alpha = 1.0 - (1.0 - 0.01) ** 128
+    assert abs(alpha - 0.7237483323) < 1e-10
+    assert np.max(np.abs(rgba[:, 3] - alpha)) < 1e-12
+    c = [np.interp(0.5, np.arange(256) / 255.0, lut[:, ch].astype(np.float64)) for ch in range(3)]
+    assert np.max(np.abs(rgba[:, :3] - np.array(c)[None])) < 1e-12
+
+
+def test_avip_early_termination_index():
+    """Alg. AVIP0 stops after the first sample whose alpha exceeds 0.99: with a = 0.1,
+    alpha_43 = 0.98922 and alpha_44 = 0.99030, so exactly 44 samples are composited."""
+    n = 64
+    cube = np.full((n, n, n), 0.5, np.float32)
+    cam = synth.ortho_axis(n, n, n, 4, 4, "+z")
+    lut = synth.lut_ramp(256)
+    rgba, frag, ns = oracle.render(cube, cam, lut, dict(mode="avip0", lo=0.0, hi=1.0, k=0.2))
+    assert abs((1 - 0.9 ** 43) - 0.98922) < 1e-5 and abs((1 - 0.9 ** 44) - 0.99030) < 1e-5
+    assert (ns == 44).all()
+    assert np.max(np.abs(rgba[:, 3] - (1 - 0.9 ** 44))) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["avip0", "avip1", "aviprgb"])
+def test_avip_equals_premultiplied_emission_absorption(mode):
+    """With the minVal clamp inactive, the paper's normalised recurrence equals the textbook
+    front-to-back emission-absorption sum C' = C + c a (1 - A), A' = A + a (1 - A), with the
+    output colour C/A.  Samples come from library interpolation at closed-form positions."""
+    n = 24
+    cube = synth.blob_cube(n, 3, seed=2)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    lut = synth.lut_heat(128)
+    k = 0.31
+    rgba, _, ns = oracle.render(cube, cam, lut, dict(mode=mode, lo=lo, hi=hi, k=k, ert=0.99))
+    x, y, zs = ortho_z_samples(n, n, n)
+    grid = np.arange(128) / 127.0
+    tab = lambda s, ch: np.interp(s, grid, lut[:, ch].astype(np.float64))  # noqa: E731
+    for p in range(0, n * n, 7):
+        pts = np.stack([np.full_like(zs, x[p]), np.full_like(zs, y[p]), zs], 1)
+        s = norm01(scipy_trilinear(cube, pts), lo, hi)
+        Cp = np.zeros(3)
+        A = 0.0
+        cnt = 0
+        for kk in range(len(zs)):
+            if mode == "avip0":
+                col = np.array([tab(s[kk], ch) for ch in range(3)])
+            else:
+                loc = np.clip((pts[kk] + 0.5) / n, 0, 1)
+                col = (np.array([tab(loc[2], ch) for ch in range(3)]) if mode == "avip1"
+                       else np.array([loc[2], loc[1], loc[0]]))
+            a = k * s[kk]
+            Cp += col * a * (1 - A)
+            A += a * (1 - A)
+            cnt += 1
+            if A > 0.99:
+                break
+        assert ns[p] == cnt
+        assert abs(rgba[p, 3] - A) < 1e-12
+        assert np.max(np.abs(rgba[p, :3] - Cp / A)) < 1e-10
+
+
+def test_avip_gradient_closed_form_uniform():
+    """d alpha_n / d a = n (1 - a)^(n-1) for the uniform cube (Eq. AVIP unrolled), pushed to
+    the transfer function's alpha control points through a = k * tf(s).a."""
+    n = 32
+    cube = np.full((n, n, n), 0.5, np.float32)
+    cam = synth.ortho_axis(n, n, n, 2, 2, "+z")
+    M = 5
+    tf = np.full((M, 4), 0.3)
+    k = 0.1
+    a = k * 0.3
+    g = np.zeros((4, 4))
+    g[:, 3] = 1.0
+    rgba, gtf, gvox = oracle.render_grad(cube, cam, tf, dict(lo=0.0, hi=1.0, k=k, ert=2.0), g)
+    N = 64
+    assert np.allclose(rgba[:, 3], 1 - (1 - a) ** N)
+    dA_da = N * (1 - a) ** (N - 1)
+    # s = 0.5 -> x = 2.0 -> interval j0 = 2, f = 0: all weight on control point 2
+    assert abs(gtf[2, 3] - 4 * dA_da * k) < 1e-10
+    assert np.allclose(np.delete(gtf[:, 3], 2), 0.0)
+
+
+def test_avip_gradient_matches_central_differences():
+    """The oracle's reverse pass agrees with central finite differences of its own forward
+    pass (h = 1e-6) for transfer-function control points and voxel values."""
+    cube = synth.gradcheck_cube(0, n=12).astype(np.float64)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.perspective_lookat(12, 12, 12, 30.0, 20.0, 30.0, 40.0, 6, 6)
+    M = 8
+    tf = synth.tf_bumps(M, seed=1).astype(np.float64) * 0.9 + 0.05
+    params = dict(lo=lo, hi=hi, k=0.4, ert=0.99, dt=0.5)
+    rng = np.random.default_rng(0)
+    grad = rng.standard_normal((36, 4))
+    rgba, gtf, gvox = oracle.render_grad(cube, cam, tf, params, grad)
+
+    def loss(tf_, cube_):
+        p = dict(params, mode="avip0", opacity_from_lut=1)
+        r, frag, _ = oracle.render(cube_, cam, tf_, p, margins=dict(da=1e-4))
+        return float((r * grad).sum()), frag
+
+    _, frag = loss(tf, cube)
+    h = 1e-6
+    for (j, ch) in [(1, 0), (3, 3), (5, 1), (6, 2), (2, 3)]:
+        tp, tm = tf.copy(), tf.copy()
+        tp[j, ch] += h
+        tm[j, ch] -= h
+        fd = (loss(tp, cube)[0] - loss(tm, cube)[0]) / (2 * h)
+        assert abs(fd - gtf[j, ch]) <= 1e-6 * max(1.0, abs(fd))
+    idx = np.argsort(-np.abs(gvox).ravel())[:6]
+    for i in idx:
+        cp, cm = cube.copy().ravel(), cube.copy().ravel()
+        cp[i] += h
+        cm[i] -= h
+        fd = (loss(tf, cp.reshape(cube.shape))[0] - loss(tf, cm.reshape(cube.shape))[0]) / (2 * h)
+        assert abs(fd - gvox.ravel()[i]) <= 1e-6 * max(1.0, abs(fd))
+
+
+# ------------------------------------------------------------------ filters (P10)
+def test_filters_reduce_to_identity_when_inactive():
+    """Clipping with minT below and maxT above the data, domain scaling over [lo, hi],
+    and box smoothing of a constant cube all leave the render unchanged."""
+    cube = synth.cfg0_cube(2)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.perspective_lookat(64, 64, 64, 20.0, 10.0, 120.0, 40.0, 48, 32)
+    lut = synth.lut_heat(256)
+    for mode in ("mip0", "mip1", "avip0", "aviprgb"):
+        base, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=lo, hi=hi))
+        clip, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=lo, hi=hi, filter="clip",
+                                                         min_t=lo - 1, max_t=hi + 1))
+        scale, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=lo, hi=hi,
+                                                          filter="scale", min_t=lo, max_t=hi))
+        assert np.max(np.abs(base - clip)) == 0.0
+        assert np.max(np.abs(base - scale)) < 1e-12
+    const = np.full((16, 16, 16), 0.37, np.float32)
+    cam2 = synth.perspective_lookat(16, 16, 16, 40.0, 30.0, 40.0, 40.0, 16, 16)
+    for mode in ("mip1", "avip0"):
+        a, _, _ = oracle.render(const, cam2, lut, dict(mode=mode, lo=0, hi=1))
+        b, _, _ = oracle.render(const, cam2, lut, dict(mode=mode, lo=0, hi=1, box_arm=3))
+        assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_clip_and_scale_follow_the_algorithms():
+    """Alg. intensity clipping: a fetched value below minT or above maxT becomes DATAMIN
+    (s = 0).  Alg. domain scaling: out of [minT, maxT] -> DATAMIN, inside
+    (v - minT)/(maxT - minT).  Both act on the interpolated sample (Alg. 1 filter())."""
+    n = 8
+    rng = np.random.default_rng(1)
+    cube = rng.uniform(0, 10, (n, n, n)).astype(np.float32)
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    lut = synth.lut_ramp(256)
+    lo, hi = quant.finite_minmax(cube)
+    x, y, zs = ortho_z_samples(n, n, n)
+    rc, _, _ = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi, filter="clip",
+                                                  min_t=3.0, max_t=7.0))
+    rs, _, _ = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi, filter="scale",
+                                                  min_t=3.0, max_t=7.0))
+    for p in range(n * n):
+        pts = np.stack([np.full_like(zs, x[p]), np.full_like(zs, y[p]), zs], 1)
+        v = scipy_trilinear(cube, pts)
+        out = (v < 3.0) | (v > 7.0)
+        kept = np.where(out, lo, v).max()
+        assert abs(rc[p, 0] - norm01(kept, lo, hi)) < 1e-7
+        sc = np.where(out, 0.0, (v - 3.0) / 4.0).max()
+        assert abs(rs[p, 0] - sc) < 1e-7
+
+
+def test_box_smoothing_is_mean_along_the_ray():
+    """Section 4.1: with filterArm a the value at sample k is the mean of the samples at
+    k-a..k+a along the ray; axis-aligned, that is a running mean of library samples."""
+    n = 12
+    cube = synth.blob_cube(n, 2, seed=9)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    lut = synth.lut_ramp(256)
+    a = 2
+    r, _, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=lo, hi=hi, box_arm=a))
+    x, y, zs = ortho_z_samples(n, n, n)
+    zext = -0.5 + 0.5 * np.arange(-a, len(zs) + a)
+    for p in range(0, n * n, 5):
+        pts = np.stack([np.full_like(zext, x[p]), np.full_like(zext, y[p]), zext], 1)
+        v = scipy_trilinear(cube, pts)
+        mean = np.convolve(v, np.ones(2 * a + 1) / (2 * a + 1), mode="valid")
+        assert abs(r[p, 0] - norm01(mean.max(), lo, hi)) < 1e-7
+
+
+# ------------------------------------------------------------------ misses (P14)
+def test_missing_rays_and_backward_camera_give_zero():
+    cube = synth.cfg0_cube(0)
+    lut = synth.lut_ramp(256)
+    away = synth.Camera(1, (31.5, 31.5, -50.0), (0.2, 0, 0), (0, 0.2, 0), (0, 0, -1.0), 8, 8)
+    r, _, ns = oracle.render(cube, away, lut, dict(mode="avip0", lo=-5, hi=20))
+    assert np.all(r == 0) and np.all(ns == 0)
+    side = synth.Camera(0, (100.0, 31.5, 31.5), (0, 5, 0), (0, 0, 5), (1.0, 0, 0), 8, 8)
+    r, _, ns = oracle.render(cube, side, lut, dict(mode="mip0", lo=-5, hi=20))
+    assert np.all(r == 0) and np.all(ns == 0)
+
+
+def test_eye_inside_volume_starts_at_eye():
+    cube = synth.cfg0_cube(0)
+    lut = synth.lut_ramp(256)
+    cam = synth.Camera(1, (31.5, 31.5, 31.5), (0.3, 0, 0), (0, 0.3, 0), (0, 0, 1.0), 2, 2)
+    _, _, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=-5, hi=20, dt=0.5))
+    o, d = oracle.pixel_ray(cam, 0, 0)
+    t0, t1 = oracle.ray_box(cube.shape, o, d)
+    assert t0 == 0.0
+    assert ns[0] == math.ceil(t1 / 0.5)
+
+
+# ------------------------------------------------------------------ line ratio (P8, P9)
+def test_line_ratio_of_gaussian_lines_closed_form():
+    """Section 4.5 method 2 per voxel: two Gaussian lines A1 g(z; c, s1), A2 g(z; c, s2) have
+    ratio (A2/A1) exp(-(z - c)^2 (1/s2^2 - 1/s1^2)/2); equal widths give a constant A2/A1."""
+    n, nz = 20, 40
+    l1, l2 = synth.two_line_pair(n, nz, ratio=0.4, sig1=3.0, sig2=2.0)
+    cube = np.concatenate([l1, l2], axis=0)
+    R = oracle.line_ratio(cube, 0, nz, nz, datamin=-1.0)
+    z = np.arange(nz)[:, None, None]
+    c = nz / 2.0
+    ref = 0.4 * np.exp(-((z - c) ** 2) * (1 / 2.0 ** 2 - 1 / 3.0 ** 2) / 2.0)
+    ok = l1 > 1e-200
+    assert np.max(np.abs(R - np.broadcast_to(ref, R.shape))[ok] / ref.max()) < 1e-10
+
+
+def test_ratio_render_methods_on_proportional_lines():
+    """Method 1 (ratio of maxima, strict '>') and method 2 (MIP of per-sample ratios) both
+    return A2/A1 when the two lines have equal widths, at any viewing angle."""
+    n, nz = 16, 24
+    l1, l2 = synth.two_line_pair(n, nz, ratio=0.45, sig1=2.5, sig2=2.5, amp=2.0)
+    l1 = l1 + 0.05  # keep cube 1 positive everywhere so every sample is defined
+    l2 = l2 + 0.45 * 0.05
+    lut = synth.lut_ramp(256)
+    cam = synth.perspective_lookat(n, n, nz, 25.0, 15.0, 50.0, 40.0, 20, 20)
+    for method in (1, 2):
+        r, frag, ns = oracle.render(l1, cam, lut, dict(mode="mip0", ratio=method, lo=0.0, hi=1.0,
+                                                       ratio_lo=0.0, ratio_hi=1.0), cube2=l2)
+        hit = ns > 0
+        assert hit.sum() > 100
+        assert np.max(np.abs(r[hit, 0] - 0.45)) < 1e-7
+
+
+def test_ratio_of_a_cube_with_itself_is_one():
+    cube = synth.cfg0_cube(0)
+    R = oracle.line_ratio(cube, 10, 10, 20, datamin=-99.0)
+    pos = cube[10:30] > 0
+    assert np.all(R[pos] == 1.0)
+    assert np.all(R[~pos] == -99.0)
+
+
+# ------------------------------------------------------------------ smoothing (P6, P7)
+def test_binomial_taps_are_pascal_rows():
+    """Section 4.2: b_n = [1, 1]^{*n} is the binomial series (Pascal's triangle)."""
+    for T in (3, 5, 9, 13):
+        n = T - 1
+        ref = np.array([math.comb(n, j) for j in range(T)], dtype=np.float64) / 2.0 ** n
+        assert np.array_equal(taps.binomial(T), ref)
+
+
+def test_paper9_printed_constants_are_trimmed_b12():
+    """The printed 9-tap weights/offsets (Section 4.2, golden fixture) are the linear-sampling
+    form of b_12 with its two outermost taps per side dropped and renormalised:
+    [66, 220, 495, 792, 924, 792, 495, 220, 66] / 4070."""
+    g = json.load(open(os.path.join(GOLDEN, "paper9_taps.json")))
+    assert taps.PAPER9_CENTRE_WEIGHT == g["coeff0"]
+    assert taps.PAPER9_PAIRS == ((g["off1"], g["coeff1"]), (g["off2"], g["coeff2"]))
+    ref = np.array([66, 220, 495, 792, 924, 792, 495, 220, 66], dtype=np.float64) / 4070.0
+    b12 = np.array([math.comb(12, j) for j in range(13)], dtype=np.float64)[2:11]
+    assert np.allclose(b12 / b12.sum(), ref, atol=0)
+    assert np.max(np.abs(taps.paper9() - ref)) < 5e-10  # printed to 10 digits
+    f = json.load(open(os.path.join(GOLDEN, "fetch_counts.json")))
+    per_axis = 1 + 2 * len(taps.PAPER9_PAIRS)
+    assert 3 * (per_axis - 1) + 1 == f["gauss"]["9"]
+
+
+def test_paper9_linear_sampling_equals_direct_sum_on_a_row():
+    """Applying the shader's 5 linear-sampled fetches to a random row equals the 9-tap
+    discrete sum with the expanded taps (interpolation by numpy.interp)."""
+    rng = np.random.default_rng(0)
+    row = rng.standard_normal(64)
+    xs = np.arange(64)
+    t = taps.paper9()
+    for c in range(10, 54):
+        shader = g0 = taps.PAPER9_CENTRE_WEIGHT * row[c]
+        for off, w in taps.PAPER9_PAIRS:
+            shader += w * (np.interp(c + off, xs, row) + np.interp(c - off, xs, row))
+        direct = float(np.dot(t, row[c - 4:c + 5]))
+        assert abs(shader - direct) < 1e-12 + 0 * g0
+
+
+def test_gaussian_taps_and_fwhm():
+    """Eq. Gaussian (isotropic) and Eq. FWHM: the sampled kernel is symmetric with unit sum
+    and variance close to sigma^2; the continuous profile is half maximum at FWHM/2."""
+    for sigma in (1.0, 2.0, 3.0):
+        g = taps.gauss(sigma)
+        r = len(g) // 2
+        assert len(g) == 2 * math.ceil(3 * sigma) + 1
+        assert np.allclose(g, g[::-1]) and abs(g.sum() - 1) < 1e-15
+        a = np.arange(-r, r + 1)
+        var = float((g * a * a).sum())
+        assert abs(var - sigma ** 2) / sigma ** 2 < 0.03
+        h = taps.fwhm(sigma) / 2.0
+        assert abs(math.exp(-h * h / (2 * sigma * sigma)) - 0.5) < 1e-15
+
+
+def test_smooth_separable_equals_library_and_triple_sum():
+    """Section 4.2 successive 1D convolution per axis with clamp-to-edge equals scipy's 1D
+    correlation along each axis (mode 'nearest') and the direct triple sum; a constant
+    cube is unchanged and a centred delta returns the kernel g x g x g."""
+    rng = np.random.default_rng(2)
+    cube = rng.standard_normal((11, 13, 16))
+    for g in (taps.binomial(5), taps.gauss(1.0), taps.paper9()):
+        out = oracle.smooth(cube, g)
+        ref = cube
+        for ax in (2, 1, 0):
+            ref = ndimage.correlate1d(ref, g, axis=ax, mode="nearest")
+        assert np.max(np.abs(out - ref)) < 1e-13
+        idx = rng.choice(cube.size, 50, replace=False)
+        assert np.max(np.abs(oracle.smooth_at(cube, g, idx) - out.ravel()[idx])) < 1e-13
+    const = np.full((9, 9, 9), 3.25)
+    assert np.max(np.abs(oracle.smooth(const, taps.gauss(2.0)) - 3.25)) < 1e-14
+    g = taps.gauss(1.0)
+    r = len(g) // 2
+    delta = np.zeros((15, 15, 15))
+    delta[7, 7, 7] = 1.0
+    out = oracle.smooth(delta, g)
+    kern = np.einsum("i,j,k->ijk", g, g, g)
+    assert np.max(np.abs(out[7 - r:8 + r, 7 - r:8 + r, 7 - r:8 + r] - kern)) < 1e-16
+
+
+# ------------------------------------------------------------------ storage (N1)
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(0)
+    a = np.concatenate([rng.standard_normal(10000).astype(np.float32) * 100,
+                        np.array([0.0, -0.0, 1e-40, np.inf, -np.inf, 3.0e38], np.float32)])
+    ours = quant.to_bf16_as_f32(a)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(ours.view(np.uint32), ref.view(np.uint32))
+    assert np.isnan(quant.to_bf16_as_f32(np.array([np.nan], np.float32))).all()
+
+
+def test_finite_minmax_ignores_nan():
+    cube = synth.nan_mosaic_cube(32, 32, 8)
+    lo, hi = quant.finite_minmax(cube)
+    f = cube[np.isfinite(cube)]
+    assert lo == f.min() and hi == f.max() and np.isnan(cube).any()
