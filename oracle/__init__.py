@@ -45,7 +45,11 @@ class _Params(C.Structure):
 
 class _Margins(C.Structure):
     _fields_ = [("ds", C.c_double), ("dv", C.c_double), ("da", C.c_double),
-                ("dn", C.c_double), ("dr", C.c_double)]
+                ("dn", C.c_double), ("dr", C.c_double), ("pv", C.c_double),
+                ("pt", C.c_double), ("pp", C.c_double)]
+
+
+FRAG_COUNT, FRAG_ARGMAX, FRAG_ERT, FRAG_THRESHOLD, FRAG_RATIO, FRAG_COND = 1, 2, 4, 8, 16, 32
 
 
 _lib = None
@@ -61,8 +65,8 @@ def lib():
         P = C.POINTER
         L.orc_render.argtypes = [P(C.c_double), P(C.c_double), C.c_int32, C.c_int32, C.c_int32,
                                  P(_Camera), P(C.c_double), C.c_int32, P(_Params), P(_Margins),
-                                 C.c_int64, P(C.c_int64), P(C.c_double), P(C.c_uint8),
-                                 P(C.c_int32), C.c_int32]
+                                 C.c_int64, P(C.c_int64), P(C.c_int32), P(C.c_double),
+                                 P(C.c_uint8), P(C.c_int32), C.c_int32]
         L.orc_render_grad.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32,
                                       P(_Camera), P(C.c_double), C.c_int32, P(_Params),
                                       C.c_int64, P(C.c_int64), P(C.c_double), P(C.c_double),
@@ -129,11 +133,14 @@ def params_struct(params):
     return p
 
 
-DEFAULT_MARGINS = dict(ds=1e-5, dv=1e-5, da=2e-5, dn=1e-9, dr=0.0)
+DEFAULT_MARGINS = dict(ds=1e-5, dv=1e-5, da=2e-6, dn=1e-9, dr=0.0, pv=0.0, pt=5e-6, pp=0.0)
 
 
-def render(cube, camera, lut, params, cube2=None, pixels=None, margins=None, nthreads=0):
-    """FP64 render.  Returns (rgba[npix,4] float64, fragile[npix] bool, nsamples[npix])."""
+def render(cube, camera, lut, params, cube2=None, pixels=None, margins=None, nthreads=0,
+           forced_n=None, bits=False):
+    """FP64 render.  Returns (rgba[npix,4] float64, fragile[npix], nsamples[npix]);
+    fragile is boolean, or the FRAG_* bit mask when bits=True.  forced_n[npix] (>= 0)
+    makes AVIP rays composite exactly that many samples."""
     V = _cube64(cube)
     V2 = _cube64(cube2) if cube2 is not None else None
     if V2 is not None and V2.shape != V.shape:
@@ -153,14 +160,19 @@ def render(cube, camera, lut, params, cube2=None, pixels=None, margins=None, nth
     rgba = np.zeros((npix, 4), dtype=np.float64)
     frag = np.zeros(npix, dtype=np.uint8)
     ns = np.zeros(npix, dtype=np.int32)
+    fn = None
+    if forced_n is not None:
+        fn = np.ascontiguousarray(forced_n, dtype=np.int32).reshape(-1)
+        assert fn.size == npix
     rc = lib().orc_render(_dp(V), _dp(V2) if V2 is not None else None, nx, ny, nz,
                           C.byref(cam), _dp(L), L.shape[0], C.byref(p), C.byref(mg), npix,
                           pix.ctypes.data_as(C.POINTER(C.c_int64)) if pix is not None else None,
+                          fn.ctypes.data_as(C.POINTER(C.c_int32)) if fn is not None else None,
                           _dp(rgba), frag.ctypes.data_as(C.POINTER(C.c_uint8)),
                           ns.ctypes.data_as(C.POINTER(C.c_int32)), int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_render rejected its arguments (code {rc})")
-    return rgba, frag.astype(bool), ns
+    return rgba, (frag if bits else frag.astype(bool)), ns
 
 
 def render_grad(cube, camera, tf, params, grad_rgba, pixels=None, want_vox=True):

@@ -115,7 +115,20 @@ typedef struct {
     const orc_params* p;
     const orc_margins* mg;
     double o[3], d[3], t0;
+    int64_t pix;     /* pixel id (seeds the conditioning probe) */
+    int pert;        /* 0: exact values; 1, 2: probe sign patterns */
 } ray_ctx;
+
+/* Deterministic +-1 for the conditioning probe (splitmix64 finaliser of pixel, sample, cube). */
+static double probe_sign(int64_t pix, int64_t k, int salt) {
+    uint64_t z = (uint64_t)pix * 0x9E3779B97F4A7C15ull;
+    z ^= (uint64_t)(k + 4099) * 0xBF58476D1CE4E5B9ull;
+    z ^= (uint64_t)salt * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    z *= 0xD6E8FEB86659FD93ull;
+    z ^= z >> 32;
+    return (z & 1u) ? 1.0 : -1.0;
+}
 
 static void ray_point(const ray_ctx* r, int64_t k, double q[3]) {
     double t = r->t0 + (double)k * r->p->dt;
@@ -133,18 +146,23 @@ static void ray_loc(const ray_ctx* r, int64_t k, double loc[3]) {
 
 /* cube[loc] followed by smooth() of Alg. 1: the box mean of the 2a+1 samples taken at the
  * ray's own positions k-a .. k+a (Section 4.1, "along the ray direction"). */
-static double ray_value(const ray_ctx* r, const double* V, int64_t k) {
-    int32_t arm = r->p->box_arm;
+static double ray_sample(const ray_ctx* r, const double* V, int64_t k, int which) {
     double q[3];
-    if (arm <= 0) {
-        ray_point(r, k, q);
-        return orc_trilinear(V, r->nx, r->ny, r->nz, q);
-    }
+    ray_point(r, k, q);
+    if (r->pert && r->mg->pp > 0.0)
+        for (int a = 0; a < 3; ++a)
+            q[a] += r->mg->pp * (fabs(q[a]) + 1.0) * probe_sign(r->pix, k, 16 * r->pert + 4 + a);
+    double v = orc_trilinear(V, r->nx, r->ny, r->nz, q);
+    if (r->pert == 1) v += r->mg->pv;  /* correlated error: every sample moved up */
+    if (r->pert == 2) v += r->mg->pv * probe_sign(r->pix, k, 16 + which);  /* random signs */
+    return v;
+}
+
+static double ray_value(const ray_ctx* r, const double* V, int64_t k, int which) {
+    int32_t arm = r->p->box_arm;
+    if (arm <= 0) return ray_sample(r, V, k, which);
     double sum = 0.0;
-    for (int64_t j = -arm; j <= arm; ++j) {
-        ray_point(r, k + j, q);
-        sum += orc_trilinear(V, r->nx, r->ny, r->nz, q);
-    }
+    for (int64_t j = -arm; j <= arm; ++j) sum += ray_sample(r, V, k + j, which);
     return sum / (double)(2 * arm + 1);
 }
 
@@ -158,7 +176,7 @@ static double ray_value(const ray_ctx* r, const double* V, int64_t k) {
 static double filter_s(const orc_params* p, double v, double dv, int* fragile, int* exact) {
     *exact = 0;
     if (p->filter == ORC_FILTER_CLIP || p->filter == ORC_FILTER_SCALE) {
-        if (fabs(v - p->min_t) < dv || fabs(v - p->max_t) < dv) *fragile = 1;
+        if (fabs(v - p->min_t) < dv || fabs(v - p->max_t) < dv) *fragile |= ORC_FRAG_THRESHOLD;
         if (p->filter == ORC_FILTER_CLIP) {
             if (v < p->min_t) { v = p->lo; *exact = 1; }
             if (v > p->max_t) { v = p->lo; *exact = 1; }
@@ -176,21 +194,23 @@ static double filter_s(const orc_params* p, double v, double dv, int* fragile, i
 static double clip_raw(const orc_params* p, double v, double mn, double mx, double dv,
                        int* fragile) {
     if (p->filter != ORC_FILTER_CLIP) return v;
-    if (fabs(v - mn) < dv || fabs(v - mx) < dv) *fragile = 1;
+    if (fabs(v - mn) < dv || fabs(v - mx) < dv) *fragile |= ORC_FRAG_THRESHOLD;
     if (v < mn) v = p->lo;
     if (v > mx) v = p->lo;
     return v;
 }
 
-static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px, int32_t py,
-                         double out[4], uint8_t* frag_out, int32_t* ns_out, double* sbuf,
-                         uint8_t* ebuf) {
+static void render_core(const ray_ctx* base, const orc_camera* cam, int32_t px, int32_t py,
+                        int pert, int32_t forced, double out[4], uint8_t* frag_out,
+                        int32_t* ns_out, double* sbuf, uint8_t* ebuf) {
     const orc_params* p = base->p;
     const orc_margins* mg = base->mg;
     ray_ctx r = *base;
     int fragile = 0;
     int64_t count = 0;
     double t1;
+    r.pix = (int64_t)py * cam->width + px;
+    r.pert = pert;
     out[0] = out[1] = out[2] = out[3] = 0.0;
     *frag_out = 0;
     if (ns_out) *ns_out = 0;
@@ -203,7 +223,7 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
     int64_t N = (int64_t)ceil(q);
     {
         double near = fabs(q - nearbyint(q));
-        if (near > 0.0 && near < mg->dn * (q > 1.0 ? q : 1.0)) fragile = 1;
+        if (near > 0.0 && near < mg->dn * (q > 1.0 ? q : 1.0)) fragile |= ORC_FRAG_COUNT;
     }
 
     if (p->ratio == 1) {
@@ -211,15 +231,15 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
          * when max1 > 0, else (0,0,0,0). */
         double m1 = -INFINITY, m2 = -INFINITY;
         for (int64_t k = 0; k < N; ++k) {
-            double v1 = clip_raw(p, ray_value(&r, r.V, k), p->min_t, p->max_t, mg->dv, &fragile);
-            double v2 = clip_raw(p, ray_value(&r, r.V2, k), p->min_t2, p->max_t2, mg->dv, &fragile);
+            double v1 = clip_raw(p, ray_value(&r, r.V, k, 0), p->min_t, p->max_t, mg->dv, &fragile);
+            double v2 = clip_raw(p, ray_value(&r, r.V2, k, 1), p->min_t2, p->max_t2, mg->dv, &fragile);
             if (v1 > m1) m1 = v1;
             if (v2 > m2) m2 = v2;
         }
         count = N;
-        if (fabs(m1) < mg->dv) fragile = 1;
+        if (fabs(m1) < mg->dv) fragile |= ORC_FRAG_THRESHOLD;
         if (m1 > 0.0) {
-            if (m1 < mg->dr) fragile = 1;
+            if (m1 < mg->dr) fragile |= ORC_FRAG_RATIO;
             double s = domain01(m2 / m1, p->ratio_lo, p->ratio_hi);
             table_at(r.lut, r.M, s, out);
             if (p->mip_alpha == 1) out[3] = 1.0;
@@ -229,13 +249,13 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
          * (s = 0); then MIP0. */
         double smax = -INFINITY;
         for (int64_t k = 0; k < N; ++k) {
-            double v1 = clip_raw(p, ray_value(&r, r.V, k), p->min_t, p->max_t, mg->dv, &fragile);
-            double v2 = clip_raw(p, ray_value(&r, r.V2, k), p->min_t2, p->max_t2, mg->dv, &fragile);
+            double v1 = clip_raw(p, ray_value(&r, r.V, k, 0), p->min_t, p->max_t, mg->dv, &fragile);
+            double v2 = clip_raw(p, ray_value(&r, r.V2, k, 1), p->min_t2, p->max_t2, mg->dv, &fragile);
             double s;
-            if (fabs(v1) < mg->dv) fragile = 1;
+            if (fabs(v1) < mg->dv) fragile |= ORC_FRAG_THRESHOLD;
             if (v1 > 0.0) {
                 s = domain01(v2 / v1, p->ratio_lo, p->ratio_hi);
-                if (s > 0.0 && s < 1.0 && v1 < mg->dr) fragile = 1;
+                if (s > 0.0 && s < 1.0 && v1 < mg->dr) fragile |= ORC_FRAG_RATIO;
             } else {
                 s = 0.0;
             }
@@ -250,7 +270,7 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
         int64_t kmax = -1;
         for (int64_t k = 0; k < N; ++k) {
             int exact;
-            double s = filter_s(p, ray_value(&r, r.V, k), mg->dv, &fragile, &exact);
+            double s = filter_s(p, ray_value(&r, r.V, k, 0), mg->dv, &fragile, &exact);
             sbuf[k] = s;
             ebuf[k] = (uint8_t)exact;
             if (s >= smax) { smax = s; kmax = k; }
@@ -274,7 +294,7 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
                         if (clampd(qk[a], 0.0, n[a] - 1.0) != clampd(qm[a], 0.0, n[a] - 1.0)) same = 0;
                     if (same) continue;
                 }
-                fragile = 1;
+                fragile |= ORC_FRAG_ARGMAX;
                 break;
             }
         }
@@ -300,7 +320,7 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
             /* Section 5.4 workaround: transparent only where the maximum is at or below
              * the minimum threshold, opaque elsewhere. */
             double sthr = domain01(p->min_t, p->lo, p->hi);
-            if (fabs(smax - sthr) < mg->ds) fragile = 1;
+            if (fabs(smax - sthr) < mg->ds) fragile |= ORC_FRAG_ARGMAX;
             if (smax > sthr) alpha = 1.0;
         }
         out[3] = alpha;
@@ -310,7 +330,7 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
         double T[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t k = 0; k < N; ++k) {
             int exact;
-            double s = filter_s(p, ray_value(&r, r.V, k), mg->dv, &fragile, &exact);
+            double s = filter_s(p, ray_value(&r, r.V, k, 0), mg->dv, &fragile, &exact);
             double tab[4], colour[3], a;
             table_at(r.lut, r.M, s, tab);
             if (p->mode == ORC_AVIP0) {
@@ -337,13 +357,37 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
             for (int ch = 0; ch < 3; ++ch) T[ch] = T[ch] * (a1 / al) + colour[ch] * (a2 / al);
             T[3] = al;
             ++count;
-            if (fabs(al - p->ert) < mg->da) fragile = 1;
+            if (forced >= 0) {
+                if (count >= forced) break;
+                continue;
+            }
+            if (fabs(al - p->ert) < mg->da) fragile |= ORC_FRAG_ERT;
             if (al > p->ert) break;
         }
         out[0] = T[0]; out[1] = T[1]; out[2] = T[2]; out[3] = T[3];
     }
     *frag_out = (uint8_t)fragile;
     if (ns_out) *ns_out = (int32_t)count;
+}
+
+static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px, int32_t py,
+                         int32_t forced, double out[4], uint8_t* frag_out, int32_t* ns_out,
+                         double* sbuf, uint8_t* ebuf) {
+    render_core(base, cam, px, py, 0, forced, out, frag_out, ns_out, sbuf, ebuf);
+    if (base->mg->pv > 0.0 || base->mg->pp > 0.0) {
+        /* conditioning probe: move every sample position and value and watch the output */
+        double worst = 0.0;
+        for (int pert = 1; pert <= 2; ++pert) {
+            double alt[4];
+            uint8_t f;
+            render_core(base, cam, px, py, pert, forced, alt, &f, NULL, sbuf, ebuf);
+            for (int ch = 0; ch < 4; ++ch) {
+                double dlt = fabs(alt[ch] - out[ch]);
+                if (dlt > worst) worst = dlt;
+            }
+        }
+        if (worst > base->mg->pt) *frag_out |= ORC_FRAG_COND;
+    }
 }
 
 static int check_common(int32_t nx, int32_t ny, int32_t nz, const orc_camera* cam,
@@ -358,7 +402,8 @@ static int check_common(int32_t nx, int32_t ny, int32_t nz, const orc_camera* ca
 int orc_render(const double* V, const double* V2, int32_t nx, int32_t ny, int32_t nz,
                const orc_camera* cam, const double* lut, int32_t M, const orc_params* p,
                const orc_margins* mg, int64_t npix, const int64_t* pix,
-               double* rgba, uint8_t* fragile, int32_t* nsamples, int32_t nthreads) {
+               const int32_t* forced_n, double* rgba, uint8_t* fragile, int32_t* nsamples,
+               int32_t nthreads) {
     if (!V || check_common(nx, ny, nz, cam, M, p) || !mg || !rgba || !fragile) return 1;
     if (p->ratio && !V2) return 1;
     const int64_t npx = (int64_t)cam->width * cam->height;
@@ -386,10 +431,10 @@ int orc_render(const double* V, const double* V2, int32_t nx, int32_t ny, int32_
 #pragma omp for schedule(dynamic, 64)
             for (int64_t i = 0; i < npix; ++i) {
                 int64_t id = pix ? pix[i] : i;
-                if (id < 0 || id >= npx) { fragile[i] = 1; continue; }
+                if (id < 0 || id >= npx) { fragile[i] = ORC_FRAG_COUNT; continue; }
                 int32_t px = (int32_t)(id % cam->width), py = (int32_t)(id / cam->width);
-                render_pixel(&base, cam, px, py, rgba + 4 * i, fragile + i,
-                             nsamples ? nsamples + i : NULL, sbuf, ebuf);
+                render_pixel(&base, cam, px, py, forced_n ? forced_n[i] : -1, rgba + 4 * i,
+                             fragile + i, nsamples ? nsamples + i : NULL, sbuf, ebuf);
             }
         }
         free(sbuf);

@@ -53,16 +53,34 @@ typedef struct {
     double da;  /* early termination: |alpha - ert| */
     double dn;  /* sample count: distance of L/dt from an integer, relative */
     double dr;  /* ratio denominators: |v1| below this makes the ratio ill-conditioned */
+    double pv;  /* conditioning probe: every sampled value is moved by +pv (all samples),
+                   then by +-pv (pseudo-random signs); 0 disables the probe */
+    double pt;  /* ... and the pixel is fragile when its RGBA then moves by more than pt */
+    double pp;  /* ... and every sample position coordinate x by +-pp (|x| + 1) (relative
+                   rounding scale of a float32 position) */
 } orc_margins;
+
+/* Fragility bits reported per pixel (0 = robust). */
+enum {
+    ORC_FRAG_COUNT = 1,      /* (t1 - t0)/dt within dn of an integer: N could differ by one */
+    ORC_FRAG_ARGMAX = 2,     /* MIP1/MIP_RGB: another sample within ds of the maximum */
+    ORC_FRAG_ERT = 4,        /* AVIP: alpha within da of the termination threshold */
+    ORC_FRAG_THRESHOLD = 8,  /* a filtered value within dv of minT/maxT (or of 0 for ratios) */
+    ORC_FRAG_RATIO = 16,     /* ratio denominator below dr */
+    ORC_FRAG_COND = 32       /* the +-pv / +-pp probe moved the RGBA by more than pt */
+};
 
 /* Render npix pixels (pix == NULL: all width*height pixels, row-major).  V2 is the second
  * cube for the ratio methods (NULL otherwise).  lut: M RGBA entries at j/(M-1).
- * Outputs rgba[4*npix], fragile[npix] (0/1), nsamples[npix] (may be NULL).
- * Returns 0 on success, nonzero on invalid arguments. */
+ * Outputs rgba[4*npix], fragile[npix] (ORC_FRAG_* bits), nsamples[npix] (may be NULL).
+ * forced_n (may be NULL): per pixel, when >= 0 an AVIP ray composites exactly that many
+ * samples instead of stopping at the threshold (the other reading of a near-threshold
+ * termination).  Returns 0 on success, nonzero on invalid arguments. */
 int orc_render(const double* V, const double* V2, int32_t nx, int32_t ny, int32_t nz,
                const orc_camera* cam, const double* lut, int32_t M, const orc_params* p,
                const orc_margins* mg, int64_t npix, const int64_t* pix,
-               double* rgba, uint8_t* fragile, int32_t* nsamples, int32_t nthreads);
+               const int32_t* forced_n, double* rgba, uint8_t* fragile, int32_t* nsamples,
+               int32_t nthreads);
 
 /* Ray of pixel (px, py): origin o and unit direction d.  Entry/exit of the cell-centred
  * box [-0.5, n-0.5]^3.  Returns 1 and t0 < t1 when the ray (t >= 0) meets the box. */

@@ -1,0 +1,372 @@
+// Batched rendering of many sub-cubes (each with its own camera and image) in one
+// persistent launch.
+//
+// The host builds a work queue of (volume, tile) items, ordered by an estimate of their
+// sample count (longest first), and a device table of per-volume descriptors.  A grid of
+// persistent 256-lane workgroups drains the queue: one lane claims the next item with a
+// global atomic counter, the workgroup renders that tile with the same per-ray code as
+// svr_render (so every image is bit-identical to a single-image render), and loops until
+// the queue is empty -- every workgroup exits once the counter passes the queue length.
+// The pair (counter reset kernel, persistent kernel) is captured once into a HIP graph.
+// The autotuner times tile shapes (8x32, 16x16, 32x8 pixels: four 8x8 waves) and grid
+// sizes (2, 4, 8 workgroups per CU) on the real batch and keeps the fastest.
+#include <math.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "march.h"
+
+namespace svr {
+
+struct BatchVol {
+    VolDesc v;
+    svr_camera cam;
+    float4* out;
+    int32_t tiles_x;
+};
+
+struct BatchArgs {
+    const BatchVol* vols;
+    const int2* items;     // (volume, tile)
+    int32_t nitems;
+    int32_t* counter;
+    const float4* lut;
+    int32_t lut_n;
+    svr_params p;
+    int32_t tw;            // waves per tile along x (1, 2 or 4); tile = 8*tw x 8*(4/tw)
+};
+
+__global__ void batch_reset_kernel(int32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+template <int MODE, int DT, int C>
+__global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
+    extern __shared__ float4 smem[];
+    __shared__ int s_item;
+    float4* s_lut = smem;
+    const int n_lut = b.lut_n;
+    for (int i = threadIdx.x; i < n_lut; i += kBlock) s_lut[i] = b.lut[i];
+    float* ring = reinterpret_cast<float*>(smem + n_lut) + threadIdx.x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int tw = b.tw, th = 4 / tw;
+    const int wx = w % tw, wy = w / tw;
+    for (;;) {
+        __syncthreads();  // the previous item is finished and s_item may be rewritten
+        if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= b.nitems) break;  // uniform across the workgroup
+        const int2 item = b.items[it];
+        const BatchVol& bv = b.vols[item.x];
+        const int tx = item.y % bv.tiles_x, ty = item.y / bv.tiles_x;
+        const int px = tx * (8 * tw) + wx * 8 + (l & 7);
+        const int py = ty * (8 * th) + wy * 8 + (l >> 3);
+        if (px < bv.cam.width && py < bv.cam.height) {
+            RenderArgs a;
+            a.v = bv.v;
+            a.v2 = bv.v;
+            a.cam = bv.cam;
+            a.lut = b.lut;
+            a.lut_n = n_lut;
+            a.p = b.p;
+            a.out = bv.out;
+            a.samples = nullptr;
+            a.tiles_x = 0;
+            a.nblocks = 0;
+            float4 res;
+            int count;
+            render_ray<MODE, 0, DT, C>(a, s_lut, ring, px, py, res, count);
+            bv.out[(size_t)py * bv.cam.width + px] = res;
+        }
+    }
+}
+
+using BatchFn = void (*)(BatchArgs);
+
+template <int DT, int C>
+static BatchFn batch_pick(int mode) {
+    switch (mode) {
+        case SVR_MIP0: return batch_kernel<SVR_MIP0, DT, C>;
+        case SVR_MIP1: return batch_kernel<SVR_MIP1, DT, C>;
+        case SVR_MIPRGB: return batch_kernel<SVR_MIPRGB, DT, C>;
+        case SVR_AVIP0: return batch_kernel<SVR_AVIP0, DT, C>;
+        case SVR_AVIP1: return batch_kernel<SVR_AVIP1, DT, C>;
+        default: return batch_kernel<SVR_AVIPRGB, DT, C>;
+    }
+}
+
+static BatchFn batch_pick_any(int dtype, int brick, int mode) {
+    if (brick == 16) {
+        if (dtype == SVR_F16) return batch_pick<SVR_F16, 16>(mode);
+        if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 16>(mode);
+        return batch_pick<SVR_F32, 16>(mode);
+    }
+    if (dtype == SVR_F16) return batch_pick<SVR_F16, 8>(mode);
+    if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 8>(mode);
+    return batch_pick<SVR_F32, 8>(mode);
+}
+
+// Host estimate of the samples a tile costs: the longest chord among its four corner rays
+// and its centre ray, in steps of dt (0 when all five miss).
+static double tile_cost(const svr_camera& c, const VolDesc& v, int x0, int y0, int w, int h,
+                        double dt) {
+    const int xs[5] = {x0, std::min(x0 + w - 1, c.width - 1), x0,
+                       std::min(x0 + w - 1, c.width - 1), std::min(x0 + w / 2, c.width - 1)};
+    const int ys[5] = {y0, y0, std::min(y0 + h - 1, c.height - 1),
+                       std::min(y0 + h - 1, c.height - 1), std::min(y0 + h / 2, c.height - 1)};
+    double best = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        const double u = 2.0 * (xs[i] + 0.5) / c.width - 1.0;
+        const double vv = 2.0 * (ys[i] + 0.5) / c.height - 1.0;
+        double o[3], d[3];
+        for (int a = 0; a < 3; ++a) {
+            if (c.type == 0) {
+                o[a] = c.eye[a] + u * c.U[a] + vv * c.V[a];
+                d[a] = c.W[a];
+            } else {
+                o[a] = c.eye[a];
+                d[a] = c.W[a] + u * c.U[a] + vv * c.V[a];
+            }
+        }
+        const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const int n[3] = {v.nx, v.ny, v.nz};
+        double tn = 0.0, tf = INFINITY;
+        bool hit = len > 0.0;
+        for (int a = 0; a < 3 && hit; ++a) {
+            const double da = d[a] / len;
+            if (da == 0.0) {
+                hit = o[a] >= -0.5 && o[a] <= n[a] - 0.5;
+                continue;
+            }
+            double ta = (-0.5 - o[a]) / da, tb = (n[a] - 0.5 - o[a]) / da;
+            if (ta > tb) std::swap(ta, tb);
+            tn = std::max(tn, ta);
+            tf = std::min(tf, tb);
+        }
+        if (hit && tf > tn) best = std::max(best, (tf - tn) / dt);
+    }
+    return best;
+}
+
+svr_status check_camera(const svr_camera* c);
+svr_status check_lut(const svr_lut* l);
+svr_status check_params(const svr_params* p, const svr_volume* v);
+
+}  // namespace svr
+
+using namespace svr;
+
+struct svr_batch {
+    int n = 0;
+    int mode = 0, dtype = 0, brick = 8;
+    BatchVol* d_vols = nullptr;
+    int2* d_items = nullptr;
+    int32_t* d_counter = nullptr;
+    BatchArgs args{};
+    BatchFn fn = nullptr;
+    int grid = 0;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<BatchVol> vols;
+    svr_lut lut{};
+};
+
+static void batch_free(svr_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_vols) (void)hipFree(b->d_vols);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+}
+
+// Build the cost-ordered queue for tile shape tw and upload it.
+static svr_status batch_items(svr_batch* b, int tw, hipStream_t s) {
+    const int th = 4 / tw, tile_w = 8 * tw, tile_h = 8 * th;
+    std::vector<std::pair<double, int2>> q;
+    for (int i = 0; i < b->n; ++i) {
+        BatchVol& bv = b->vols[i];
+        bv.tiles_x = (bv.cam.width + tile_w - 1) / tile_w;
+        const int tiles_y = (bv.cam.height + tile_h - 1) / tile_h;
+        for (int t = 0; t < bv.tiles_x * tiles_y; ++t) {
+            const int x0 = (t % bv.tiles_x) * tile_w, y0 = (t / bv.tiles_x) * tile_h;
+            q.push_back({tile_cost(bv.cam, bv.v, x0, y0, tile_w, tile_h, b->args.p.dt),
+                         make_int2(i, t)});
+        }
+    }
+    std::stable_sort(q.begin(), q.end(),
+                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
+                         return x.first > y.first;
+                     });
+    std::vector<int2> items(q.size());
+    for (size_t i = 0; i < q.size(); ++i) items[i] = q[i].second;
+    if (b->d_items == nullptr) {
+        hipError_t e = hipMalloc(&b->d_items, items.size() * sizeof(int2));
+        if (e != hipSuccess) return hip_fail(e, "batch queue allocation");
+        e = hipMalloc(&b->d_vols, b->vols.size() * sizeof(BatchVol));
+        if (e != hipSuccess) return hip_fail(e, "batch descriptor allocation");
+    }
+    svr_status st = hip_fail(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2),
+                                            hipMemcpyHostToDevice, s), "batch queue upload");
+    if (st) return st;
+    st = hip_fail(hipMemcpyAsync(b->d_vols, b->vols.data(), b->vols.size() * sizeof(BatchVol),
+                                 hipMemcpyHostToDevice, s), "batch descriptor upload");
+    if (st) return st;
+    // the host vectors are released on return: finish the copies first
+    st = hip_fail(hipStreamSynchronize(s), "batch upload sync");
+    b->args.nitems = (int32_t)items.size();
+    b->args.tw = tw;
+    return st;
+}
+
+static void batch_enqueue(const svr_batch* b, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
+    hipLaunchKernelGGL(b->fn, dim3(grid), dim3(kBlock), b->lds, s, b->args);
+}
+
+extern "C" {
+
+svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cams, int32_t n,
+                            const svr_lut* lut, const svr_params* params,
+                            float* const* rgba_outs, int32_t tune, void* stream,
+                            svr_batch** out) {
+    if (!vols || !cams || !rgba_outs || !out || n < 1) {
+        set_error("svr_batch_create: null argument or n < 1");
+        return SVR_EINVAL;
+    }
+    svr_status st = check_lut(lut);
+    if (st) return st;
+    if ((st = check_params(params, vols[0]))) return st;
+    if (params->ratio != 0) {
+        set_error("svr_batch_create: line-ratio methods are not batched");
+        return SVR_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (!vols[i] || !rgba_outs[i]) {
+            set_error("svr_batch_create: null volume or output %d", i);
+            return SVR_EINVAL;
+        }
+        if ((st = check_camera(&cams[i]))) return st;
+        if ((st = check_params(params, vols[i]))) return st;
+        if (vols[i]->d.dtype != vols[0]->d.dtype || vols[i]->d.brick != vols[0]->d.brick) {
+            set_error("svr_batch_create: all volumes must share storage type and brick size");
+            return SVR_EINVAL;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    svr_batch* b = new (std::nothrow) svr_batch;
+    if (!b) return SVR_ENOMEM;
+    b->n = n;
+    b->mode = params->mode;
+    b->dtype = vols[0]->d.dtype;
+    b->brick = vols[0]->d.brick;
+    b->lut = *lut;
+    b->vols.resize(n);
+    for (int i = 0; i < n; ++i) {
+        b->vols[i].v = vols[i]->d;
+        b->vols[i].cam = cams[i];
+        b->vols[i].out = reinterpret_cast<float4*>(rgba_outs[i]);
+    }
+    b->args.lut = reinterpret_cast<const float4*>(lut->rgba);
+    b->args.lut_n = lut->n;
+    b->args.p = *params;
+    b->fn = batch_pick_any(b->dtype, b->brick, b->mode);
+    b->lds = render_lds_bytes(lut->n, params->box_arm, 0);
+    hipError_t e = hipMalloc(&b->d_counter, 64);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "batch counter allocation");
+    }
+    b->args.counter = b->d_counter;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+
+    int best_tw = 2, best_grid = cus * 4;
+    if (tune) {
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        float best_ms = INFINITY;
+        const int tws[3] = {2, 4, 1};
+        const int per_cu[3] = {4, 8, 2};
+        for (int ti = 0; ti < 3 && !st; ++ti) {
+            st = batch_items(b, tws[ti], s);
+            for (int gi = 0; gi < 3 && !st; ++gi) {
+                const int grid = cus * per_cu[gi];
+                batch_enqueue(b, grid, s);  // warm-up
+                (void)hipEventRecord(e0, s);
+                batch_enqueue(b, grid, s);
+                (void)hipEventRecord(e1, s);
+                st = hip_fail(hipEventSynchronize(e1), "batch autotune");
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (!st && ms < best_ms) {
+                    best_ms = ms;
+                    best_tw = tws[ti];
+                    best_grid = grid;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    if (!st) st = batch_items(b, best_tw, s);
+    b->grid = best_grid;
+    if (!st) {
+        hipStream_t cap = nullptr;
+        st = hip_fail(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+        if (!st) {
+            st = hip_fail(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal),
+                          "begin capture");
+            if (!st) {
+                batch_enqueue(b, b->grid, cap);
+                st = hip_fail(hipStreamEndCapture(cap, &b->graph), "end capture");
+            }
+            if (!st)
+                st = hip_fail(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0),
+                              "graph instantiate");
+            (void)hipStreamDestroy(cap);
+        }
+    }
+    if (st) {
+        batch_free(b);
+        return st;
+    }
+    *out = b;
+    return SVR_OK;
+}
+
+svr_status svr_batch_launch(svr_batch* batch, void* stream) {
+    if (!batch) {
+        set_error("svr_batch_launch: null batch");
+        return SVR_EINVAL;
+    }
+    return hip_fail(hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream)),
+                    "batch graph launch");
+}
+
+svr_status svr_batch_info(const svr_batch* batch, int64_t* items, int32_t* grid,
+                          int32_t* tile_waves_x) {
+    if (!batch) {
+        set_error("svr_batch_info: null batch");
+        return SVR_EINVAL;
+    }
+    if (items) *items = batch->args.nitems;
+    if (grid) *grid = batch->grid;
+    if (tile_waves_x) *tile_waves_x = batch->args.tw;
+    return SVR_OK;
+}
+
+svr_status svr_batch_destroy(svr_batch* batch) {
+    if (batch) (void)hipDeviceSynchronize();
+    batch_free(batch);
+    return SVR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP translation units of libsvr (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "svr.h"
+
+namespace svr {
+
+constexpr int kWave = 64;
+constexpr int kTile = 16;            // image tile of one 256-lane workgroup (16 x 16 pixels)
+constexpr int kBlock = 256;
+constexpr int kCkptEvery = 32;       // samples between stored ray states (adjoint)
+
+// Device view of a bricked volume.  Brick (bx, by, bz) holds voxels [C*b, C*b + C] per axis
+// (C + 1 = E stored per axis; the last layer is the apron = first layer of the next brick,
+// or a replica of the cube's last voxel).  Element (lx, ly, lz) of a brick sits at
+// brick_index * pitch + (lz * E + ly) * E + lx, brick_index = (bz * nby + by) * nbx + bx.
+struct VolDesc {
+    const void* data;
+    int32_t nx, ny, nz;
+    int32_t nbx, nby, nbz;
+    int32_t dtype;
+    int32_t brick;        // C
+    uint32_t pitch;       // elements per brick (E^3 rounded up to 64)
+    const float* clim;    // device: [finite min, finite max] of the stored values
+};
+
+// Element loaders: stored type -> float32.
+template <int DT> struct Elem;
+template <> struct Elem<SVR_F32> {
+    using T = float;
+    static __device__ __forceinline__ float get(const T* p, uint32_t i) { return p[i]; }
+    static __device__ __forceinline__ T put(float v) { return v; }
+};
+template <> struct Elem<SVR_F16> {
+    using T = _Float16;
+    static __device__ __forceinline__ float get(const T* p, uint32_t i) { return (float)p[i]; }
+    static __device__ __forceinline__ T put(float v) { return (_Float16)v; }  // RNE
+};
+template <> struct Elem<SVR_BF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ float get(const T* p, uint32_t i) {
+        return __uint_as_float(((uint32_t)p[i]) << 16);
+    }
+    static __device__ __forceinline__ T put(float v) {  // round to nearest even; NaN stays NaN
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (T)(u >> 16);
+    }
+};
+
+__device__ __forceinline__ float med3(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Workgroup b -> tile index so that each XCD (workgroups are dealt round-robin over the
+// 8 XCDs) owns one contiguous run of tiles and its L2 sees neighbouring rays.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, s = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+// Ray of one pixel and its entry into the box [-0.5, n-0.5]^3, in double precision with
+// every operation rounded separately (no contraction), so the entry point and the sample
+// count match an IEEE double evaluation of the same formulas.  Returns the sample count
+// (0 on a miss) and the first sample position / per-sample step rounded to float.
+struct RaySeg {
+    float p0[3];
+    float step[3];
+    int32_t n;
+};
+
+__device__ inline RaySeg ray_segment(const svr_camera& c, int px, int py, int nx, int ny,
+                                     int nz, float dtf) {
+#pragma clang fp contract(off)
+    RaySeg r;
+    r.n = 0;
+    const double u = 2.0 * ((double)px + 0.5) / (double)c.width - 1.0;
+    const double v = 2.0 * ((double)py + 0.5) / (double)c.height - 1.0;
+    double o[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+        if (c.type == 0) {
+            o[a] = (double)c.eye[a] + u * (double)c.U[a] + v * (double)c.V[a];
+            d[a] = (double)c.W[a];
+        } else {
+            o[a] = (double)c.eye[a];
+            d[a] = (double)c.W[a] + u * (double)c.U[a] + v * (double)c.V[a];
+        }
+    }
+    const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    d[0] = d[0] / len;
+    d[1] = d[1] / len;
+    d[2] = d[2] / len;
+    if (!(isfinite(d[0]) && isfinite(d[1]) && isfinite(d[2]))) return r;
+    const int n[3] = {nx, ny, nz};
+    double tn = -INFINITY, tf = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = -0.5, hi = (double)n[a] - 0.5;
+        if (d[a] == 0.0) {
+            if (o[a] < lo || o[a] > hi) return r;
+            continue;
+        }
+        double ta = (lo - o[a]) / d[a];
+        double tb = (hi - o[a]) / d[a];
+        if (ta > tb) { const double t = ta; ta = tb; tb = t; }
+        if (ta > tn) tn = ta;
+        if (tb < tf) tf = tb;
+    }
+    if (tn < 0.0) tn = 0.0;
+    if (!(tf > tn)) return r;
+    const double dt = (double)dtf;
+    r.n = (int32_t)ceil((tf - tn) / dt);
+    for (int a = 0; a < 3; ++a) {
+        r.p0[a] = (float)(o[a] + tn * d[a]);
+        r.step[a] = (float)(dt * d[a]);
+    }
+    return r;
+}
+
+// Table lookup: n RGBA entries at j/(n-1), linear interpolation; s in [0, 1].
+__device__ __forceinline__ float4 table(const float4* L, int n, float s) {
+    const float x = s * (float)(n - 1);
+    int j = (int)x;
+    j = j > n - 2 ? n - 2 : j;
+    const float f = x - (float)j;
+    const float4 a = L[j], b = L[j + 1];
+    return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y),
+                       fmaf(f, b.z - a.z, a.z), fmaf(f, b.w - a.w, a.w));
+}
+
+// Host side helpers --------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+svr_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace svr
+
+// The opaque handles of the C ABI.
+struct svr_volume {
+    svr::VolDesc d;
+    void* mem;          // bricked storage
+    float* aux;         // clim[2], fill[1], partial reductions
+    int64_t bytes;
+    int device;
+};

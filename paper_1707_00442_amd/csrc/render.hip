@@ -1,0 +1,92 @@
+// Forward ray-march (Alg. 1 with the transfer functions of Section 3, the box smoothing of
+// Section 4.1, the filters of Sections 4.3/4.4 and the line-ratio methods of Section 4.5).
+//
+// One lane per ray.  A 256-lane workgroup covers a 16x16 pixel tile as four 8x8 wave tiles;
+// tiles are dealt to XCDs in contiguous runs.  Ray setup is FP64 (once per ray); the hot
+// loop is FP32: a trilinear fetch from the bricked, aproned volume (eight loads sharing one
+// address), the filter, the transfer function and compositing.  The colour table and the
+// per-lane box-smoothing ring live in LDS.  A wave leaves the loop when all its lanes are
+// done (AVIP early termination is per lane; the wave retires with its last ray).
+#include "march.h"
+
+namespace svr {
+
+template <int MODE, int RATIO, int DT, int C>
+__global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
+    extern __shared__ float4 smem[];
+    float4* s_lut = smem;
+    const int n_lut = a.lut_n;
+    for (int i = threadIdx.x; i < n_lut; i += kBlock) s_lut[i] = a.lut[i];
+    __syncthreads();
+
+    const int t = xcd_tile((int)blockIdx.x, a.nblocks);
+    const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int px = tx * kTile + (w & 1) * 8 + (l & 7);
+    const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+    if (px >= a.cam.width || py >= a.cam.height) return;
+
+    float4 res;
+    int count;
+    float* ring = reinterpret_cast<float*>(smem + n_lut) + threadIdx.x;
+    render_ray<MODE, RATIO, DT, C>(a, s_lut, ring, px, py, res, count);
+    const size_t pix = (size_t)py * a.cam.width + px;
+    a.out[pix] = res;
+    if (a.samples) a.samples[pix] = count;
+}
+
+using RenderFn = void (*)(RenderArgs);
+
+template <int DT, int C>
+static RenderFn pick(int mode, int ratio) {
+    if (ratio == 1) return render_kernel<SVR_MIP0, 1, DT, C>;
+    if (ratio == 2) return render_kernel<SVR_MIP0, 2, DT, C>;
+    switch (mode) {
+        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C>;
+        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C>;
+        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C>;
+        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C>;
+        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C>;
+        default: return render_kernel<SVR_AVIPRGB, 0, DT, C>;
+    }
+}
+
+static RenderFn pick_any(int dtype, int brick, int mode, int ratio) {
+    if (brick == 16) {
+        if (dtype == SVR_F16) return pick<SVR_F16, 16>(mode, ratio);
+        if (dtype == SVR_BF16) return pick<SVR_BF16, 16>(mode, ratio);
+        return pick<SVR_F32, 16>(mode, ratio);
+    }
+    if (dtype == SVR_F16) return pick<SVR_F16, 8>(mode, ratio);
+    if (dtype == SVR_BF16) return pick<SVR_BF16, 8>(mode, ratio);
+    return pick<SVR_F32, 8>(mode, ratio);
+}
+
+size_t render_lds_bytes(int lut_n, int box_arm, int ratio) {
+    size_t b = (size_t)lut_n * sizeof(float4);
+    if (ratio == 0 && box_arm > 0) b += (size_t)(2 * box_arm + 1) * kBlock * sizeof(float);
+    return b;
+}
+
+svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_camera& cam,
+                         const svr_lut& lut, const svr_params& p, float* out,
+                         int32_t* samples, hipStream_t stream) {
+    RenderArgs a;
+    a.v = v->d;
+    a.v2 = v2 ? v2->d : v->d;
+    a.cam = cam;
+    a.lut = reinterpret_cast<const float4*>(lut.rgba);
+    a.lut_n = lut.n;
+    a.p = p;
+    a.out = reinterpret_cast<float4*>(out);
+    a.samples = samples;
+    a.tiles_x = (cam.width + kTile - 1) / kTile;
+    const int tiles_y = (cam.height + kTile - 1) / kTile;
+    a.nblocks = a.tiles_x * tiles_y;
+    RenderFn fn = pick_any(v->d.dtype, v->d.brick, p.mode, p.ratio);
+    const size_t lds = render_lds_bytes(lut.n, p.box_arm, p.ratio);
+    hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(kBlock), lds, stream, a);
+    return hip_fail(hipGetLastError(), "render launch");
+}
+
+}  // namespace svr

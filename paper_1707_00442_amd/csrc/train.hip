@@ -1,0 +1,379 @@
+// Differentiable AVIP0 with a piecewise-linear RGBA transfer function, and its adjoint.
+//
+// Forward (train_fwd_kernel): the AVIP0 ray-march of the render path with colour = tf(s).rgb
+// and opacity weight k * tf(s).a; every 32 samples the ray state (C, A) before the sample
+// is stored, and at the end the number of composited samples K.  The image equals the
+// plain render with opacity_from_lut = 1.
+//
+// Backward (train_bwd_kernel): one wave per 8x8 pixel tile.  Each ray walks its segments
+// from the last to the first: it reloads the segment's stored state, replays the segment
+// forward keeping the per-sample state and s in LDS (32 x 20 bytes per lane), then runs the
+// reverse recurrence of the normalised compositing step.  Transfer-function gradients are
+// reduced in LDS per workgroup and flushed with one global atomic per entry; voxel
+// gradients go to the eight trilinear corners with hardware float atomics.
+#include "sampler.h"
+
+namespace svr {
+
+constexpr int kTrainMaxTf = 256;
+
+struct TrainArgs {
+    VolDesc v;
+    svr_camera cam;
+    const float4* tf;
+    int32_t tf_n;
+    svr_params p;
+    float4* out;
+    int32_t* kcount;
+    float4* ckpt;
+    int64_t nrays;
+    int32_t nseg, tiles_x, nblocks;
+    const float4* grad;
+    float* grad_tf;
+    float* grad_vox;
+};
+
+// One step of the normalised front-to-back compositing of Alg. AVIP0, as in the render path.
+struct AvipState {
+    float r, g, b, a;
+};
+
+__device__ __forceinline__ void avip_step(AvipState& t, float4 c, float kw, float minv) {
+    const float a1 = t.a;
+    const float a2 = kw * c.w * (1.0f - a1);
+    const float al = fmaxf(a1 + a2, minv);
+    const float ri = rcp(al);
+    const float w1 = a1 * ri, w2 = a2 * ri;
+    t.r = fmaf(t.r, w1, c.x * w2);
+    t.g = fmaf(t.g, w1, c.y * w2);
+    t.b = fmaf(t.b, w1, c.z * w2);
+    t.a = al;
+}
+
+template <int DT, int C>
+__global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
+    __shared__ float4 s_tf[kTrainMaxTf];
+    for (int i = threadIdx.x; i < a.tf_n; i += kBlock) s_tf[i] = a.tf[i];
+    __syncthreads();
+    const int t = xcd_tile((int)blockIdx.x, a.nblocks);
+    const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int px = tx * kTile + (w & 1) * 8 + (l & 7);
+    const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+    const int64_t rid = (int64_t)t * kBlock + threadIdx.x;
+    if (px >= a.cam.width || py >= a.cam.height) {
+        a.kcount[rid] = 0;
+        return;
+    }
+    float lo = a.p.clim_lo, hi = a.p.clim_hi;
+    if (!(hi > lo)) {
+        lo = a.v.clim[0];
+        hi = a.v.clim[1];
+    }
+    const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
+    const RaySeg r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
+    const Sampler<DT, C> smp(a.v);
+    AvipState st{0.0f, 0.0f, 0.0f, 0.0f};
+    const float kw = a.p.k, minv = a.p.min_val, ert = a.p.ert;
+    int K = 0;
+    float kf = 0.0f;
+    for (int k = 0; k < r.n; ++k, kf += 1.0f) {
+        if ((k & (kCkptEvery - 1)) == 0)
+            a.ckpt[(int64_t)(k / kCkptEvery) * a.nrays + rid] = make_float4(st.r, st.g, st.b, st.a);
+        const float v = smp(fmaf(kf, r.step[0], r.p0[0]), fmaf(kf, r.step[1], r.p0[1]),
+                            fmaf(kf, r.step[2], r.p0[2]));
+        const float s = __saturatef((v - lo) * inv);
+        avip_step(st, table(s_tf, a.tf_n, s), kw, minv);
+        ++K;
+        if (st.a > ert) break;
+    }
+    a.kcount[rid] = K;
+    a.out[(size_t)py * a.cam.width + px] = make_float4(st.r, st.g, st.b, st.a);
+}
+
+template <int DT, int C>
+__global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
+    __shared__ float4 s_tf[kTrainMaxTf];
+    __shared__ float s_gtf[kTrainMaxTf * 4];
+    __shared__ float4 s_state[kCkptEvery][kWave];
+    __shared__ float s_s[kCkptEvery][kWave];
+    const int n = a.tf_n;
+    const int l = threadIdx.x;
+    for (int i = l; i < n; i += kWave) s_tf[i] = a.tf[i];
+    for (int i = l; i < 4 * n; i += kWave) s_gtf[i] = 0.0f;
+    __syncthreads();
+
+    const int t = (int)blockIdx.x >> 2, sub = (int)blockIdx.x & 3;
+    const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+    const int px = tx * kTile + (sub & 1) * 8 + (l & 7);
+    const int py = ty * kTile + (sub >> 1) * 8 + (l >> 3);
+    const int64_t rid = (int64_t)t * kBlock + sub * kWave + l;
+    const bool inside = px < a.cam.width && py < a.cam.height;
+    const int K = inside ? a.kcount[rid] : 0;
+    if (K > 0) {
+        float lo = a.p.clim_lo, hi = a.p.clim_hi;
+        if (!(hi > lo)) {
+            lo = a.v.clim[0];
+            hi = a.v.clim[1];
+        }
+        const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
+        const RaySeg r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
+        const Sampler<DT, C> smp(a.v);
+        const float kw = a.p.k, minv = a.p.min_val;
+        const float nm1 = (float)(n - 1);
+        const float4 g = a.grad[(size_t)py * a.cam.width + px];
+        float gr = g.x, gg = g.y, gb = g.z, ga = g.w;
+        const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
+        const float xm = (float)(a.v.nx - 1), ym = (float)(a.v.ny - 1), zm = (float)(a.v.nz - 1);
+        for (int seg = (K - 1) / kCkptEvery; seg >= 0; --seg) {
+            const int k0 = seg * kCkptEvery;
+            const int k1 = min(k0 + kCkptEvery, K);
+            const float4 c0 = a.ckpt[(int64_t)seg * a.nrays + rid];
+            AvipState st{c0.x, c0.y, c0.z, c0.w};
+            // replay the segment, keeping the state before each sample
+            for (int k = k0; k < k1; ++k) {
+                const float kf = (float)k;
+                const float v = smp(fmaf(kf, r.step[0], r.p0[0]), fmaf(kf, r.step[1], r.p0[1]),
+                                    fmaf(kf, r.step[2], r.p0[2]));
+                const float s = __saturatef((v - lo) * inv);
+                s_state[k - k0][l] = make_float4(st.r, st.g, st.b, st.a);
+                s_s[k - k0][l] = s;
+                avip_step(st, table(s_tf, n, s), kw, minv);
+            }
+            // reverse recurrence
+            for (int k = k1 - 1; k >= k0; --k) {
+                const float4 S0 = s_state[k - k0][l];
+                const float s = s_s[k - k0][l];
+                const float4 c = table(s_tf, n, s);
+                const float a_ = kw * c.w;
+                const float a1 = S0.w;
+                const float a2 = a_ * (1.0f - a1);
+                const float sum = a1 + a2;
+                const bool active = sum >= minv;
+                const float al = fmaxf(sum, minv);
+                const float ri = rcp(al);
+                const float w1 = a1 * ri, w2 = a2 * ri;
+                const float C1r = fmaf(S0.x, w1, c.x * w2);
+                const float C1g = fmaf(S0.y, w1, c.y * w2);
+                const float C1b = fmaf(S0.z, w1, c.z * w2);
+                const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
+                const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (active ? g_al : 0.0f);
+                const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri +
+                                   (active ? g_al : 0.0f) - g_a2 * a_;
+                const float gcr = gr * w2, gcg = gg * w2, gcb = gb * w2;
+                const float gop = kw * g_a2 * (1.0f - a1);
+                // table: interval j, weight f (as in the forward lookup)
+                const float x = s * nm1;
+                int j = (int)x;
+                j = j > n - 2 ? n - 2 : j;
+                const float f = x - (float)j;
+                const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
+                atomicAdd(&s_gtf[4 * j + 0], (1.0f - f) * gcr);
+                atomicAdd(&s_gtf[4 * j + 1], (1.0f - f) * gcg);
+                atomicAdd(&s_gtf[4 * j + 2], (1.0f - f) * gcb);
+                atomicAdd(&s_gtf[4 * j + 3], (1.0f - f) * gop);
+                atomicAdd(&s_gtf[4 * j + 4], f * gcr);
+                atomicAdd(&s_gtf[4 * j + 5], f * gcg);
+                atomicAdd(&s_gtf[4 * j + 6], f * gcb);
+                atomicAdd(&s_gtf[4 * j + 7], f * gop);
+                if (a.grad_vox != nullptr && s > 0.0f && s < 1.0f) {
+                    const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
+                                      gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
+                    const float gv = gs * inv;
+                    const float kf = (float)k;
+                    const float px_ = med3(fmaf(kf, r.step[0], r.p0[0]), 0.0f, xm);
+                    const float py_ = med3(fmaf(kf, r.step[1], r.p0[1]), 0.0f, ym);
+                    const float pz_ = med3(fmaf(kf, r.step[2], r.p0[2]), 0.0f, zm);
+                    const float x0 = floorf(px_), y0 = floorf(py_), z0 = floorf(pz_);
+                    const float fx = px_ - x0, fy = py_ - y0, fz = pz_ - z0;
+                    const uint32_t i0 = (uint32_t)x0, j0 = (uint32_t)y0, l0 = (uint32_t)z0;
+                    const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1);
+                    const uint32_t l1 = min(l0 + 1, nz - 1);
+                    const size_t r00 = ((size_t)l0 * ny + j0) * nx, r10 = ((size_t)l0 * ny + j1) * nx;
+                    const size_t r01 = ((size_t)l1 * ny + j0) * nx, r11 = ((size_t)l1 * ny + j1) * nx;
+                    const float gx0 = gv * (1.0f - fx), gx1 = gv * fx;
+                    const float wy0z0 = (1.0f - fy) * (1.0f - fz), wy1z0 = fy * (1.0f - fz);
+                    const float wy0z1 = (1.0f - fy) * fz, wy1z1 = fy * fz;
+                    float* G = a.grad_vox;
+                    unsafeAtomicAdd(G + r00 + i0, gx0 * wy0z0);
+                    unsafeAtomicAdd(G + r00 + i1, gx1 * wy0z0);
+                    unsafeAtomicAdd(G + r10 + i0, gx0 * wy1z0);
+                    unsafeAtomicAdd(G + r10 + i1, gx1 * wy1z0);
+                    unsafeAtomicAdd(G + r01 + i0, gx0 * wy0z1);
+                    unsafeAtomicAdd(G + r01 + i1, gx1 * wy0z1);
+                    unsafeAtomicAdd(G + r11 + i0, gx0 * wy1z1);
+                    unsafeAtomicAdd(G + r11 + i1, gx1 * wy1z1);
+                }
+                gr *= w1;
+                gg *= w1;
+                gb *= w1;
+                ga = g_a1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = l; i < 4 * n; i += kWave) {
+        const float v = s_gtf[i];
+        if (v != 0.0f) unsafeAtomicAdd(a.grad_tf + i, v);
+    }
+}
+
+// ------------------------------------------------------------------------------- host side
+svr_status check_camera(const svr_camera* c);
+svr_status check_lut(const svr_lut* l);
+svr_status check_params(const svr_params* p, const svr_volume* v);
+
+static svr_status train_checks(const svr_volume* vol, const svr_camera* cam,
+                               const svr_params* p) {
+    if (!vol) {
+        set_error("null volume");
+        return SVR_EINVAL;
+    }
+    svr_status st = check_camera(cam);
+    if (st) return st;
+    if ((st = check_params(p, vol))) return st;
+    if (p->mode != SVR_AVIP0 || p->filter != SVR_FILTER_NONE || p->box_arm != 0 ||
+        p->ratio != 0 || p->opacity_from_lut != 1) {
+        set_error("differentiable render: mode SVR_AVIP0, filter none, box_arm 0, ratio 0, "
+                  "opacity_from_lut 1");
+        return SVR_EINVAL;
+    }
+    return SVR_OK;
+}
+
+struct TrainGeom {
+    int tiles_x, nblocks, nseg;
+    int64_t nrays;
+    size_t bytes;
+};
+
+static TrainGeom train_geom(const svr_volume* v, const svr_camera& cam, float dt) {
+    TrainGeom g;
+    g.tiles_x = (cam.width + kTile - 1) / kTile;
+    g.nblocks = g.tiles_x * ((cam.height + kTile - 1) / kTile);
+    g.nrays = (int64_t)g.nblocks * kBlock;
+    const double diag = sqrt((double)v->d.nx * v->d.nx + (double)v->d.ny * v->d.ny +
+                             (double)v->d.nz * v->d.nz);
+    const int64_t maxn = (int64_t)ceil(diag / (double)dt) + 2;
+    g.nseg = (int)((maxn + kCkptEvery - 1) / kCkptEvery);
+    g.bytes = 256 + (size_t)g.nrays * sizeof(int32_t) + (size_t)g.nseg * g.nrays * sizeof(float4);
+    return g;
+}
+
+template <int DT, int C>
+static void train_launch(bool fwd, const TrainArgs& a, hipStream_t s) {
+    if (fwd)
+        hipLaunchKernelGGL((train_fwd_kernel<DT, C>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((train_bwd_kernel<DT, C>), dim3(a.nblocks * 4), dim3(kWave), 0, s, a);
+}
+
+static void train_dispatch(bool fwd, int dtype, int brick, const TrainArgs& a, hipStream_t s) {
+    if (brick == 16) {
+        if (dtype == SVR_F16) train_launch<SVR_F16, 16>(fwd, a, s);
+        else if (dtype == SVR_BF16) train_launch<SVR_BF16, 16>(fwd, a, s);
+        else train_launch<SVR_F32, 16>(fwd, a, s);
+    } else {
+        if (dtype == SVR_F16) train_launch<SVR_F16, 8>(fwd, a, s);
+        else if (dtype == SVR_BF16) train_launch<SVR_BF16, 8>(fwd, a, s);
+        else train_launch<SVR_F32, 8>(fwd, a, s);
+    }
+}
+
+}  // namespace svr
+
+using namespace svr;
+
+extern "C" {
+
+svr_status svr_render_train_workspace(const svr_volume* vol, const svr_camera* cam,
+                                      const svr_params* params, size_t* bytes) {
+    svr_status st = train_checks(vol, cam, params);
+    if (st) return st;
+    if (!bytes) {
+        set_error("null output");
+        return SVR_EINVAL;
+    }
+    *bytes = train_geom(vol, *cam, params->dt).bytes;
+    return SVR_OK;
+}
+
+svr_status svr_render_train(const svr_volume* vol, const svr_camera* cam, const svr_lut* tf,
+                            const svr_params* params, float* rgba_out, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    svr_status st = train_checks(vol, cam, params);
+    if (st) return st;
+    if ((st = check_lut(tf))) return st;
+    if (tf->n > kTrainMaxTf) {
+        set_error("differentiable render: transfer function of %d > %d points", tf->n, kTrainMaxTf);
+        return SVR_EINVAL;
+    }
+    if (!rgba_out || !workspace) {
+        set_error("null output or workspace");
+        return SVR_EINVAL;
+    }
+    const TrainGeom g = train_geom(vol, *cam, params->dt);
+    if (workspace_bytes < g.bytes) {
+        set_error("workspace %zu < %zu bytes", workspace_bytes, g.bytes);
+        return SVR_ENOMEM;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TrainArgs a{};
+    a.v = vol->d;
+    a.cam = *cam;
+    a.tf = reinterpret_cast<const float4*>(tf->rgba);
+    a.tf_n = tf->n;
+    a.p = *params;
+    a.out = reinterpret_cast<float4*>(rgba_out);
+    a.kcount = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 256);
+    a.ckpt = reinterpret_cast<float4*>(static_cast<char*>(workspace) + 256 +
+                                       (size_t)g.nrays * sizeof(int32_t));
+    a.nrays = g.nrays;
+    a.nseg = g.nseg;
+    a.tiles_x = g.tiles_x;
+    a.nblocks = g.nblocks;
+    train_dispatch(true, vol->d.dtype, vol->d.brick, a, s);
+    return hip_fail(hipGetLastError(), "train forward launch");
+}
+
+svr_status svr_render_backward(const svr_volume* vol, const svr_camera* cam, const svr_lut* tf,
+                               const svr_params* params, const void* workspace,
+                               size_t workspace_bytes, const float* grad_rgba,
+                               float* grad_tf, float* grad_vox, void* stream) {
+    svr_status st = train_checks(vol, cam, params);
+    if (st) return st;
+    if ((st = check_lut(tf))) return st;
+    if (tf->n > kTrainMaxTf) {
+        set_error("differentiable render: transfer function of %d > %d points", tf->n, kTrainMaxTf);
+        return SVR_EINVAL;
+    }
+    if (!workspace || !grad_rgba || !grad_tf) {
+        set_error("null workspace, grad_rgba or grad_tf");
+        return SVR_EINVAL;
+    }
+    const TrainGeom g = train_geom(vol, *cam, params->dt);
+    if (workspace_bytes < g.bytes) {
+        set_error("workspace %zu < %zu bytes", workspace_bytes, g.bytes);
+        return SVR_ENOMEM;
+    }
+    TrainArgs a{};
+    a.v = vol->d;
+    a.cam = *cam;
+    a.tf = reinterpret_cast<const float4*>(tf->rgba);
+    a.tf_n = tf->n;
+    a.p = *params;
+    a.kcount = reinterpret_cast<int32_t*>(static_cast<char*>(const_cast<void*>(workspace)) + 256);
+    a.ckpt = reinterpret_cast<float4*>(static_cast<char*>(const_cast<void*>(workspace)) + 256 +
+                                       (size_t)g.nrays * sizeof(int32_t));
+    a.nrays = g.nrays;
+    a.nseg = g.nseg;
+    a.tiles_x = g.tiles_x;
+    a.nblocks = g.nblocks;
+    a.grad = reinterpret_cast<const float4*>(grad_rgba);
+    a.grad_tf = grad_tf;
+    a.grad_vox = grad_vox;
+    train_dispatch(false, vol->d.dtype, vol->d.brick, a, static_cast<hipStream_t>(stream));
+    return hip_fail(hipGetLastError(), "train backward launch");
+}
+
+}  // extern "C"
