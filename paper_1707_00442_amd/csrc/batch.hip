@@ -164,6 +164,7 @@ struct svr_batch {
     int mode = 0, dtype = 0, brick = 8;
     BatchVol* d_vols = nullptr;
     int2* d_items = nullptr;
+    size_t items_cap = 0;
     int32_t* d_counter = nullptr;
     BatchArgs args{};
     BatchFn fn = nullptr;
@@ -205,10 +206,20 @@ static svr_status batch_items(svr_batch* b, int tw, hipStream_t s) {
                      });
     std::vector<int2> items(q.size());
     for (size_t i = 0; i < q.size(); ++i) items[i] = q[i].second;
-    if (b->d_items == nullptr) {
+    // the queue length depends on the tile shape: (re)allocate when this one is longer
+    if (items.size() > b->items_cap) {
+        if (b->d_items) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(b->d_items);
+            b->d_items = nullptr;
+            b->items_cap = 0;
+        }
         hipError_t e = hipMalloc(&b->d_items, items.size() * sizeof(int2));
         if (e != hipSuccess) return hip_fail(e, "batch queue allocation");
-        e = hipMalloc(&b->d_vols, b->vols.size() * sizeof(BatchVol));
+        b->items_cap = items.size();
+    }
+    if (b->d_vols == nullptr) {
+        hipError_t e = hipMalloc(&b->d_vols, b->vols.size() * sizeof(BatchVol));
         if (e != hipSuccess) return hip_fail(e, "batch descriptor allocation");
     }
     svr_status st = hip_fail(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2),
@@ -219,14 +230,24 @@ static svr_status batch_items(svr_batch* b, int tw, hipStream_t s) {
     if (st) return st;
     // the host vectors are released on return: finish the copies first
     st = hip_fail(hipStreamSynchronize(s), "batch upload sync");
+    b->args.items = b->d_items;
+    b->args.vols = b->d_vols;
     b->args.nitems = (int32_t)items.size();
     b->args.tw = tw;
     return st;
 }
 
-static void batch_enqueue(const svr_batch* b, int grid, hipStream_t s) {
+static svr_status batch_enqueue(const svr_batch* b, int grid, hipStream_t s) {
+    // every table the persistent kernel reads must be in place and sized for the queue
+    if (!b->args.items || !b->args.vols || !b->args.counter || !b->args.lut ||
+        (size_t)b->args.nitems > b->items_cap || b->args.nitems < 1 ||
+        !(b->args.tw == 1 || b->args.tw == 2 || b->args.tw == 4) || grid < 1) {
+        set_error("batch: internal queue not ready");
+        return SVR_EINVAL;
+    }
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_counter);
     hipLaunchKernelGGL(b->fn, dim3(grid), dim3(kBlock), b->lds, s, b->args);
+    return hip_fail(hipGetLastError(), "batch launch");
 }
 
 extern "C" {
@@ -299,9 +320,11 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
             st = batch_items(b, tws[ti], s);
             for (int gi = 0; gi < 3 && !st; ++gi) {
                 const int grid = cus * per_cu[gi];
-                batch_enqueue(b, grid, s);  // warm-up
+                st = batch_enqueue(b, grid, s);  // warm-up
+                if (st) break;
                 (void)hipEventRecord(e0, s);
-                batch_enqueue(b, grid, s);
+                st = batch_enqueue(b, grid, s);
+                if (st) break;
                 (void)hipEventRecord(e1, s);
                 st = hip_fail(hipEventSynchronize(e1), "batch autotune");
                 float ms = 0.0f;
@@ -325,8 +348,9 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
             st = hip_fail(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal),
                           "begin capture");
             if (!st) {
-                batch_enqueue(b, b->grid, cap);
+                const svr_status sq = batch_enqueue(b, b->grid, cap);
                 st = hip_fail(hipStreamEndCapture(cap, &b->graph), "end capture");
+                if (sq) st = sq;
             }
             if (!st)
                 st = hip_fail(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0),
