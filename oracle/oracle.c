@@ -116,7 +116,8 @@ typedef struct {
     const orc_margins* mg;
     double o[3], d[3], t0;
     int64_t pix;     /* pixel id (seeds the conditioning probe) */
-    int pert;        /* 0: exact values; 1, 2: probe sign patterns */
+    int pert;        /* 0: exact values; 1..4: probe patterns */
+    int64_t nsamp;   /* samples on this ray (the ramp pattern spans them) */
 } ray_ctx;
 
 /* Deterministic +-1 for the conditioning probe (splitmix64 finaliser of pixel, sample, cube). */
@@ -155,6 +156,11 @@ static double ray_sample(const ray_ctx* r, const double* V, int64_t k, int which
     double v = orc_trilinear(V, r->nx, r->ny, r->nz, q);
     if (r->pert == 1) v += r->mg->pv;  /* correlated error: every sample moved up */
     if (r->pert == 2) v += r->mg->pv * probe_sign(r->pix, k, 16 + which);  /* random signs */
+    if (r->pert == 3) v += which ? -r->mg->pv : r->mg->pv;  /* the two cubes move apart */
+    if (r->pert == 4) {  /* an error growing along the ray, as position rounding does */
+        const double span = r->nsamp > 1 ? (double)(r->nsamp - 1) : 1.0;
+        v += r->mg->pv * (2.0 * (double)k / span - 1.0);
+    }
     return v;
 }
 
@@ -221,6 +227,7 @@ static void render_core(const ray_ctx* base, const orc_camera* cam, int32_t px, 
     /* Reading: samples t_k = t0 + k dt, k = 0 .. N-1, N = ceil((t1 - t0)/dt). */
     double q = (t1 - r.t0) / p->dt;
     int64_t N = (int64_t)ceil(q);
+    r.nsamp = N;
     {
         double near = fabs(q - nearbyint(q));
         if (near > 0.0 && near < mg->dn * (q > 1.0 ? q : 1.0)) fragile |= ORC_FRAG_COUNT;
@@ -377,7 +384,8 @@ static void render_pixel(const ray_ctx* base, const orc_camera* cam, int32_t px,
     if (base->mg->pv > 0.0 || base->mg->pp > 0.0) {
         /* conditioning probe: move every sample position and value and watch the output */
         double worst = 0.0;
-        for (int pert = 1; pert <= 2; ++pert) {
+        for (int pert = 1; pert <= 4; ++pert) {
+            if (pert == 3 && !base->V2) continue;
             double alt[4];
             uint8_t f;
             render_core(base, cam, px, py, pert, forced, alt, &f, NULL, sbuf, ebuf);

