@@ -1,0 +1,501 @@
+#!/usr/bin/env python
+"""Benchmark of the ray-cast colouring/filtering hot path on one MI355X.
+
+Workload (one step): the 512 x 512 x 1024 float32 HI-like cube (noise + 50 rotating discs,
+seed 0) seen by a perspective camera at 1920 x 1080 from the next view of a full rotation
+(azimuth step 10 deg, elevation 20 deg, distance twice the half-diagonal, vertical field of
+view 40 deg), dt = 0.5 voxel:
+  * separable 3D Gaussian smoothing with sigma = 1, 2, 3 voxels (three passes each);
+  * upload of the cube into the bricked float32 volume (finite min/max, NaN fill, apron);
+  * the six transfer functions (MIP0, MIP1, MIP_RGB, AVIP0, AVIP1, AVIP_RGB; k = 0.22,
+    clipping at minT = 3 sigma);
+  * the voxel-wise line ratio of the spectral windows [400, 432) and [600, 632), and the
+    two in-ray line-ratio methods over those windows.
+value = ray samples processed per second over the whole step (samples counted per pixel
+by the renderer itself, verified against the oracle in the tests).
+
+Further forms are timed after the main loop (reported, not part of `value`): float16 and
+bfloat16 storage, the differentiable forward + adjoint, and the batched persistent launch
+of 512 sub-cubes.  The oracle (FP64, C, OpenMP) is timed on a bounded sample of pixels of
+the same workload on this machine's host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("ray samples/sec and frames/sec @1920x1080 (fwd, fwd+bwd) vs FP32 plain; "
+          "HBM GB/s")
+PEAK_HBM = 8.0e12            # bytes/s
+PEAK_ALU = 256 * 64 * 2.4e9  # VALU lane operations/s (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz)
+
+# Algorithmic VALU operations per sample (the arithmetic the method itself needs; address
+# generation, loads and loop control are not counted).  Shared by every transfer function:
+# position 3 (p0 + k step), clamp 3, cell 3 (floor), fraction 3, trilinear 14 (7 lerps of
+# sub + fma) = 26; clipping filter 3 (two compares, one select) + normalise 1 (fma with
+# clamp) = 4.  MIP0 adds 1 (max), MIP1/MIP_RGB 3 (compare + 2 selects).  AVIP adds the
+# compositing step 14 (alpha2 2, alpha 2, rcp 1, weights 2, colour 6, termination 1) and
+# its opacity 1, plus the colour: table lookup 11 (scale, floor, fraction, 4 lerps) for
+# AVIP0 and AVIP1 (AVIP1 also 2 for loc.z), 3 for AVIP_RGB (loc).
+OPS_PER_SAMPLE = {"mip0": 31, "mip1": 33, "miprgb": 33, "avip0": 56, "avip1": 58,
+                  "aviprgb": 48, "ratio1": 26 * 2 + 6 + 2, "ratio2": 26 * 2 + 6 + 4}
+MODES = ("mip0", "mip1", "miprgb", "avip0", "avip1", "aviprgb")
+KERNEL_SOURCES = ("common.h", "sampler.h", "march.h", "render.hip")
+
+
+def source_hash(names=KERNEL_SOURCES):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1707_00442_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile", default=None,
+                    help="run only this kernel on the main workload, --steps times (for "
+                         "rocprofv3): render_<mode>, render_sparse, smooth_sigma<s>, upload, "
+                         "line_ratio, copy (a 1 GiB device copy used to scale the counters)")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every svr call is enqueued on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.spans = {}
+
+    def span(self, name):
+        t = self.torch
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        outer = self
+
+        class _S:
+            def __enter__(self):
+                e0.record()
+
+            def __exit__(self, *a):
+                e1.record()
+                outer.spans.setdefault(name, []).append((e0, e1))
+        return _S()
+
+    def ms(self, name):
+        return [a.elapsed_time(b) for a, b in self.spans.get(name, [])]
+
+
+def roofline_entry(bound, achieved, peak, unit, traffic=None):
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic}
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy kernel of known size), if recorded for the current source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel)
+        if e and e.get("source_hash") == source_hash():
+            return e.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (the multi-GPU split is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1707_00442_amd as svr
+    import synth
+    from paper_1707_00442_amd import taps as tapgen
+
+    torch.cuda.set_device(0)
+    svr.lib()
+    t_setup = time.time()
+    nx, ny, nz = 512, 512, 1024
+    W, H = 1920, 1080
+    log("building the 512x512x1024 cube")
+    cube_np = synth.cfg1_cube(0)
+    cube = torch.from_numpy(cube_np).cuda()
+    lo, hi = svr.svr_minmax(cube)
+    views = [v.as_f32() for v in synth.rotation_views(nx, ny, nz, W, H)]
+    lut = torch.from_numpy(synth.lut_heat(256)).cuda()
+    vol = svr.svr_volume_create(cube, storage="f32")
+    win_a, win_b = cube[400:432], cube[600:632]
+    vol_a = svr.svr_volume_create(win_a.contiguous())
+    vol_b = svr.svr_volume_create(win_b.contiguous())
+    ratio_views = [v.as_f32() for v in synth.rotation_views(nx, ny, 32, W, H)]
+    taps = {s: tapgen.gauss(float(s)).astype(np.float32) for s in (1, 2, 3)}
+    smooth_out = torch.empty_like(cube)
+    ws = torch.empty(svr.svr_smooth_workspace(cube), dtype=torch.uint8, device="cuda")
+    ratio_out = torch.empty((32, ny, nx), dtype=torch.float32, device="cuda")
+    imgs = {m: torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for m in MODES}
+    rimg = {r: torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for r in (1, 2)}
+    params = {m: dict(mode=m, k=0.22, filter="clip", min_t=3.0, clim_lo=lo, clim_hi=hi)
+              for m in MODES}
+    rlo, rhi = svr.svr_volume_clim(vol_a)
+    rparams = {r: dict(mode="mip0", ratio=r, filter="clip", min_t=3.0, min_t2=3.0,
+                       clim_lo=rlo, clim_hi=rhi, ratio_lo=0.0, ratio_hi=2.0) for r in (1, 2)}
+
+    K, Wu = args.steps, args.warmup
+    if args.profile:
+        return profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps,
+                           smooth_out, ws, ratio_out, lo)
+    # per-pixel sample counts of every render the timed steps will run (untimed)
+    log("counting samples per view")
+    samples = {}
+    for i in range(Wu, Wu + K):
+        cam = views[i % len(views)]
+        for m in MODES:
+            _, ns = svr.svr_render(vol, cam, lut, params[m], samples=True)
+            samples[(i, m)] = int(ns.sum().item())
+        rc = ratio_views[i % len(ratio_views)]
+        for r in (1, 2):
+            _, ns = svr.svr_render(vol_a, rc, lut, rparams[r], vol2=vol_b, samples=True)
+            samples[(i, f"ratio{r}")] = int(ns.sum().item())
+    torch.cuda.synchronize()
+
+    timer = Timer(torch)
+
+    def step(i, timed):
+        cam = views[i % len(views)]
+        tm = timer if timed else None
+
+        def span(name):
+            return tm.span(name) if tm else _Null()
+        for s in (1, 2, 3):
+            with span(f"smooth_sigma{s}"):
+                svr.svr_smooth(cube, taps[s], out=smooth_out, workspace=ws)
+        with span("upload"):
+            svr.svr_volume_upload(vol, cube)
+        for m in MODES:
+            with span(f"render_{m}"):
+                svr.svr_render(vol, cam, lut, params[m], out=imgs[m])
+        with span("line_ratio"):
+            svr.svr_line_ratio(cube, 400, 600, 32, min_t_a=3.0, min_t_b=3.0, datamin=lo,
+                               out=ratio_out)
+        rc = ratio_views[i % len(ratio_views)]
+        for r in (1, 2):
+            with span(f"render_ratio{r}"):
+                svr.svr_render(vol_a, rc, lut, rparams[r], vol2=vol_b, out=rimg[r])
+
+    log(f"warmup {Wu} steps")
+    for i in range(Wu):
+        step(i, False)
+    torch.cuda.synchronize()
+    log(f"timing {K} steps")
+    t0 = time.perf_counter()
+    for i in range(Wu, Wu + K):
+        step(i, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / K
+    total_samples = sum(samples.values())
+    value = total_samples / elapsed
+    render_samples = sum(v for (i, m), v in samples.items() if m in MODES)
+    frames = K * len(MODES)
+
+    # per-kernel figures from the HIP events
+    nvox = nx * ny * nz
+    kernels = {}
+    for m in MODES + ("ratio1", "ratio2"):
+        ms = timer.ms(f"render_{m}")
+        ns = [samples[(i, m)] for i in range(Wu, Wu + K)]
+        ops = np.array(ns, dtype=np.float64) * OPS_PER_SAMPLE[m]
+        kernels[f"render_{m}"] = dict(
+            ms_mean=float(np.mean(ms)), samples_per_s=float(np.sum(ns) / (np.sum(ms) * 1e-3)),
+            fps=float(1e3 / np.mean(ms)),
+            alu_ops_per_s=float(np.sum(ops) / (np.sum(ms) * 1e-3)))
+    for s in (1, 2, 3):
+        ms = timer.ms(f"smooth_sigma{s}")
+        kernels[f"smooth_sigma{s}"] = dict(ms_mean=float(np.mean(ms)),
+                                           hbm_bytes_algorithmic=24 * nvox,
+                                           gbps=24 * nvox / (np.mean(ms) * 1e-3) / 1e9)
+    ms = timer.ms("upload")
+    kernels["upload"] = dict(ms_mean=float(np.mean(ms)), hbm_bytes_algorithmic=8 * nvox,
+                             gbps=8 * nvox / (np.mean(ms) * 1e-3) / 1e9)
+    ms = timer.ms("line_ratio")
+    nr = 32 * nx * ny
+    kernels["line_ratio"] = dict(ms_mean=float(np.mean(ms)), hbm_bytes_algorithmic=12 * nr,
+                                 gbps=12 * nr / (np.mean(ms) * 1e-3) / 1e9)
+    # dominant kernel: the largest share of the step
+    share = {k: v["ms_mean"] for k, v in kernels.items()}
+    dominant = max(share, key=share.get)
+    if dominant.startswith("render_"):
+        m = dominant[len("render_"):]
+        ach = kernels[dominant]["alu_ops_per_s"] / 1e12
+        roof = roofline_entry("alu", ach, PEAK_ALU / 1e12, "Tops/s",
+                              load_traffic(dominant))
+        roof["kernel"] = dominant
+        roof["ops_per_sample"] = OPS_PER_SAMPLE[m]
+    else:
+        ach = kernels[dominant]["gbps"]
+        roof = roofline_entry("hbm", ach, PEAK_HBM / 1e9, "GB/s", load_traffic(dominant))
+        roof["kernel"] = dominant
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": K,
+        "warmup": Wu, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "HI-like cube 512x512x1024 float32 (noise + 50 discs, seed 0); "
+                               "perspective 1920x1080 rotation views, dt 0.5; per step: "
+                               "smooth sigma 1,2,3 + upload + 6 transfer functions (clip "
+                               "minT 3) + line ratio windows [400,432)/[600,632) (pass and "
+                               "two in-ray methods)",
+                   "image": [W, H], "cube": [nx, ny, nz], "dt": 0.5},
+        "fps_render": frames / (sum(sum(timer.ms(f"render_{m}")) for m in MODES) * 1e-3),
+        "render_samples_per_s": render_samples / (sum(sum(timer.ms(f"render_{m}"))
+                                                       for m in MODES) * 1e-3),
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    log(f"main: {value:.4g} samples/s, {ms_per_step:.2f} ms/step, dominant {dominant}")
+
+    if not args.no_forms:
+        out["forms"] = run_forms(torch, svr, synth, cube, lo, hi, views, lut, params,
+                                 kernels, args)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cube_np, views[Wu], synth, lo, hi, args)
+    log(f"total {time.time() - t_setup:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+def sparse_camera(synth):
+    """Parallel view along +z, 256x256 over the 512x512 face, dt = 1: 0.25 samples per
+    voxel, every voxel touched once (the HBM-bound corner of the ray-march)."""
+    return synth.ortho_axis(512, 512, 1024, 256, 256, "+z").as_f32()
+
+
+def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, smooth_out, ws,
+                ratio_out, lo):
+    name = args.profile
+    cam = views[0]
+    if name == "copy":
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        fn = lambda: b.copy_(a)  # noqa: E731
+    elif name == "render_sparse":
+        c = sparse_camera(synth)
+        p = dict(params["mip0"], dt=1.0)
+        fn = lambda: svr.svr_render(vol, c, lut, p)  # noqa: E731
+    elif name.startswith("render_"):
+        m = name[len("render_"):]
+        fn = lambda: svr.svr_render(vol, cam, lut, params[m])  # noqa: E731
+    elif name.startswith("smooth_sigma"):
+        s = int(name[-1])
+        fn = lambda: svr.svr_smooth(cube, taps[s], out=smooth_out, workspace=ws)  # noqa: E731
+    elif name == "upload":
+        fn = lambda: svr.svr_volume_upload(vol, cube)  # noqa: E731
+    elif name == "line_ratio":
+        fn = lambda: svr.svr_line_ratio(cube, 400, 600, 32, 3.0, 3.0, lo, out=ratio_out)  # noqa: E731,E501
+    else:
+        raise SystemExit(f"unknown kernel {name}")
+    for i in range(args.steps):
+        fn()
+        torch.cuda.synchronize()
+        log(f"profile {name}: call {i + 1}/{args.steps} done")
+    print(json.dumps({"profiled": name, "calls": args.steps, "source_hash": source_hash()}))
+
+
+class _Null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args):
+    forms = {}
+    cam = views[0]
+    plain = {}
+    vol32 = _vol32(svr, cube)
+    for m in ("mip0", "avip0"):
+        _, ns = svr.svr_render(vol32, cam, lut, params[m], samples=True)
+        n = int(ns.sum().item())
+        ms = _time(torch, lambda: svr.svr_render(vol32, cam, lut, params[m]), 5)
+        plain[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fps=1e3 / ms)
+    forms["fp32_plain"] = plain
+    # low sample density: HBM-bound ray-march
+    c = sparse_camera(synth)
+    p = dict(params["mip0"], dt=1.0)
+    _, ns = svr.svr_render(vol32, c, lut, p, samples=True)
+    n = int(ns.sum().item())
+    ms = _time(torch, lambda: svr.svr_render(vol32, c, lut, p), 10)
+    nbytes = 4 * cube.numel()
+    forms["sparse_mip0"] = dict(ms=ms, samples=n, samples_per_voxel=n / cube.numel(),
+                                samples_per_s=n / (ms * 1e-3),
+                                hbm_bytes_algorithmic=nbytes,
+                                gbps=nbytes / (ms * 1e-3) / 1e9,
+                                hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM)
+    # float16 / bfloat16 storage (FP32 arithmetic)
+    for st in ("f16", "bf16"):
+        log(f"form: {st} storage")
+        v = svr.svr_volume_create(cube, storage=st)
+        r = {}
+        for m in ("mip0", "avip0"):
+            _, ns = svr.svr_render(v, cam, lut, params[m], samples=True)
+            n = int(ns.sum().item())
+            ms = _time(torch, lambda: svr.svr_render(v, cam, lut, params[m]), 5)
+            r[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fps=1e3 / ms,
+                        speedup_vs_fp32=plain[m]["ms"] / ms)
+        forms[f"{st}_storage"] = r
+        v.close()
+    vol32.close()
+    # differentiable forward + adjoint: 256^3 cube, 64-point transfer function
+    log("form: forward + adjoint")
+    c4 = torch.from_numpy(synth.cfg4_cube(0)).cuda()
+    l4, h4 = svr.svr_minmax(c4)
+    v4 = svr.svr_volume_create(c4)
+    tf = torch.from_numpy(synth.tf_ramp(64)).cuda()
+    p4 = dict(mode="avip0", opacity_from_lut=1, k=0.22, clim_lo=l4, clim_hi=h4)
+    fb = {}
+    for (w, h) in ((1024, 1024), (1920, 1080)):
+        cam4 = synth.perspective_lookat(256, 256, 256, 30.0, 20.0, 256 * 3 ** 0.5, 40.0,
+                                        w, h).as_f32()
+        img, wsp = svr.svr_render_train(v4, cam4, tf, p4)
+        _, ns = svr.svr_render(v4, cam4, tf, p4, samples=True)
+        n = int(ns.sum().item())
+        g = torch.randn(h, w, 4, device="cuda")
+        gtf = torch.zeros_like(tf)
+        gvox = torch.zeros_like(c4)
+        ms_f = _time(torch, lambda: svr.svr_render(v4, cam4, tf, p4), 5)
+        ms_t = _time(torch, lambda: svr.svr_render_train(v4, cam4, tf, p4, out=img,
+                                                          workspace=wsp), 5)
+        ms_b = _time(torch, lambda: svr.svr_render_backward(v4, cam4, tf, p4, wsp, g,
+                                                             grad_tf=gtf, grad_vox=gvox), 3)
+        fb[f"{w}x{h}"] = dict(samples=n, fwd_ms=ms_f, train_fwd_ms=ms_t, bwd_ms=ms_b,
+                              fwd_fps=1e3 / ms_f, fwd_bwd_fps=1e3 / (ms_t + ms_b),
+                              fwd_samples_per_s=n / (ms_f * 1e-3),
+                              fwd_bwd_samples_per_s=n / ((ms_t + ms_b) * 1e-3),
+                              fwd_bwd_vs_fwd=(ms_t + ms_b) / ms_f)
+    forms["fwd_bwd"] = fb
+    v4.close()
+    # batched: 512 float16 sub-cubes, 512x512 each, one persistent graph launch
+    log("form: batched sub-cubes")
+    forms["batched"] = run_batched(torch, svr, synth, lut)
+    return forms
+
+
+def _vol32(svr, cube):
+    return svr.svr_volume_create(cube, storage="f32")
+
+
+def _make_sub(spec):
+    import synth
+    return synth.subcube(spec)
+
+
+def run_batched(torch, svr, synth, lut):
+    from concurrent.futures import ProcessPoolExecutor
+    specs = synth.subcube_batch_specs(512, 0)
+    t = time.time()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        cubes = list(ex.map(_make_sub, specs, chunksize=8))
+    log(f"  generated 512 sub-cubes in {time.time() - t:.1f}s")
+    vols, cams = [], []
+    for sp, c in zip(specs, cubes):
+        tc = torch.from_numpy(c).cuda()
+        vols.append(svr.svr_volume_create(tc, storage="f16"))
+        v = sp["view"] / np.linalg.norm(sp["view"])
+        radius = 0.5 * math.sqrt(sp["nx"] ** 2 + sp["ny"] ** 2 + sp["nz"] ** 2)
+        centre = ((sp["nx"] - 1) / 2, (sp["ny"] - 1) / 2, (sp["nz"] - 1) / 2)
+        cams.append(synth.perspective_direction(centre, v, 2 * radius, 30.0, 512, 512).as_f32())
+    del cubes
+    res = {}
+    for m in ("mip0", "avip0"):
+        p = dict(mode=m, k=0.22)
+        b = svr.svr_batch_create(vols, cams, lut, p, tune=True)
+        n = 0
+        for v, c in zip(vols, cams):
+            _, ns = svr.svr_render(v, c, lut, p, samples=True)
+            n += int(ns.sum().item())
+        ms_b = _time(torch, lambda: b.launch(), 3)
+        outs = b.outs
+
+        def per_cube():
+            for v, c, o in zip(vols, cams, outs):
+                svr.svr_render(v, c, lut, p, out=o)
+        ms_p = _time(torch, per_cube, 3)
+        res[m] = dict(samples=n, batched_ms=ms_b, per_cube_launches_ms=ms_p,
+                      speedup=ms_p / ms_b, samples_per_s=n / (ms_b * 1e-3),
+                      items=b.items, grid=b.grid, tile_waves_x=b.tile_waves_x)
+        b.close()
+    for v in vols:
+        v.close()
+    return res
+
+
+def cpu_baseline(cube_np, cam, synth, lo, hi, args):
+    """The FP64 oracle on a bounded sample of pixels of the same frame (MIP0 and AVIP0)."""
+    import oracle
+    log("CPU baseline: oracle on sampled pixels")
+    cube64 = cube_np.astype(np.float64)
+    lut = synth.lut_heat(256)
+    threads = os.cpu_count() or 1
+    rng = np.random.default_rng(0)
+    total_s, total_n, total_px = 0.0, 0, 0
+    budget = args.cpu_seconds
+    for m in ("mip0", "avip0"):
+        p = dict(mode=m, k=0.22, filter="clip", min_t=3.0, lo=lo, hi=hi)
+        npx = 512
+        while True:
+            pix = rng.choice(cam.width * cam.height, npx, replace=False)
+            t = time.perf_counter()
+            _, _, ns = oracle.render(cube64, cam, lut, p, pixels=pix, nthreads=threads)
+            dt = time.perf_counter() - t
+            if dt > 0.25 * budget or npx >= cam.width * cam.height:
+                break
+            npx = int(min(cam.width * cam.height, npx * max(2.0, 0.4 * budget / max(dt, 1e-3))))
+        total_s += dt
+        total_n += int(ns.sum())
+        total_px += npx
+    return {"value": total_n / total_s, "unit": "samples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{total_px} random pixels of the 1920x1080 frame (MIP0 and AVIP0, clip "
+                      f"minT 3) on the 512x512x1024 cube, {total_n} samples in {total_s:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

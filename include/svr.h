@@ -85,6 +85,10 @@ typedef struct svr_volume svr_volume;
 svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t brick,
                              float nan_fill, void* stream, svr_volume** out);
 svr_status svr_volume_destroy(svr_volume* vol);
+/* Re-upload a cube of the same dims into an existing volume (same storage and brick, no
+ * allocation): the upload pass alone, asynchronous on `stream`. */
+svr_status svr_volume_upload(svr_volume* vol, const svr_cube_view* src, float nan_fill,
+                             void* stream);
 /* dims_zyx[3] = (nz, ny, nx); bytes = device bytes held.  Host-only query. */
 svr_status svr_volume_info(const svr_volume* vol, int32_t* dims_zyx, int32_t* storage,
                            int32_t* brick, int64_t* bytes);

@@ -160,6 +160,12 @@ def svr_volume_destroy(vol):
     vol.close()
 
 
+def svr_volume_upload(vol, cube, nan_fill=float("nan"), stream=None):
+    v = cube_view(cube)
+    _check(lib().svr_volume_upload(vol, C.byref(v), float(nan_fill), _stream(stream)),
+           "svr_volume_upload")
+
+
 def svr_volume_info(vol):
     dims = (C.c_int32 * 3)()
     st, br = C.c_int32(), C.c_int32()

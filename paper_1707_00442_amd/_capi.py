@@ -18,7 +18,8 @@ SVR_MAX_TAPS = 63
 # every symbol include/svr.h declares
 EXPORTS = (
     "svr_status_string", "svr_last_error", "svr_version", "svr_minmax",
-    "svr_volume_create", "svr_volume_destroy", "svr_volume_info", "svr_volume_clim",
+    "svr_volume_create", "svr_volume_destroy", "svr_volume_upload", "svr_volume_info",
+    "svr_volume_clim",
     "svr_volume_export", "svr_params_validate", "svr_render", "svr_smooth_workspace",
     "svr_smooth",
     "svr_line_ratio", "svr_render_train_workspace", "svr_render_train",
@@ -73,6 +74,7 @@ def load():
         "svr_minmax": (C.c_int, [P(CubeView), P(f32), vp]),
         "svr_volume_create": (C.c_int, [P(CubeView), i32, i32, f32, vp, P(vp)]),
         "svr_volume_destroy": (C.c_int, [vp]),
+        "svr_volume_upload": (C.c_int, [vp, P(CubeView), f32, vp]),
         "svr_volume_info": (C.c_int, [vp, P(i32), P(i32), P(i32), P(i64)]),
         "svr_volume_clim": (C.c_int, [vp, P(f32), vp]),
         "svr_volume_export": (C.c_int, [vp, vp, vp]),

@@ -179,7 +179,7 @@ svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t 
     d.pitch = (uint32_t)(((E * E * E) + 63) / 64 * 64);
     const uint64_t nbricks = (uint64_t)d.nbx * d.nby * d.nbz;
     const uint64_t elems = nbricks * d.pitch;
-    if (elems >= (1ull << 32) || nbricks >= (1ull << 31)) {
+    if (elems >= (1ull << 32) || nbricks >= (1ull << 24)) {
         set_error("volume of %llu stored elements exceeds 2^32", (unsigned long long)elems);
         return SVR_EUNSUPPORTED;
     }
@@ -213,6 +213,20 @@ svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t 
     }
     *out = v;
     return SVR_OK;
+}
+
+svr_status svr_volume_upload(svr_volume* vol, const svr_cube_view* src, float nan_fill,
+                             void* stream) {
+    SVR_CHECK(vol != nullptr, "svr_volume_upload: null volume");
+    svr_status st = check_view(src, "svr_volume_upload");
+    if (st) return st;
+    SVR_CHECK(src->nx == vol->d.nx && src->ny == vol->d.ny && src->nz == vol->d.nz,
+              "svr_volume_upload: dims %d x %d x %d differ from the volume's", src->nx, src->ny,
+              src->nz);
+    SVR_CHECK(!isinf(nan_fill), "nan_fill must be finite or NaN");
+    st = launch_minmax(*src, vol->aux + 4, vol->aux, 0, vol->d.dtype, nan_fill, S(stream));
+    if (st) return st;
+    return launch_brick(*src, vol->d, vol->aux, S(stream));
 }
 
 svr_status svr_volume_destroy(svr_volume* vol) {

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
         const int tx = item.y % bv.tiles_x, ty = item.y / bv.tiles_x;
         const int px = tx * (8 * tw) + wx * 8 + (l & 7);
         const int py = ty * (8 * th) + wy * 8 + (l >> 3);
-        if (px < bv.cam.width && py < bv.cam.height) {
+        const bool inside = px < bv.cam.width && py < bv.cam.height;
+        {
             RenderArgs a;
             a.v = bv.v;
             a.v2 = bv.v;
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
             a.nblocks = 0;
             float4 res;
             int count;
-            render_ray<MODE, 0, DT, C>(a, s_lut, ring, px, py, res, count);
-            bv.out[(size_t)py * bv.cam.width + px] = res;
+            render_ray<MODE, 0, DT, C>(a, s_lut, ring, px, py, inside, res, count);
+            if (inside) bv.out[(size_t)py * bv.cam.width + px] = res;
         }
     }
 }

@@ -56,6 +56,8 @@ __device__ __forceinline__ float med3(float x, float lo, float hi) {
     return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// True when the predicate holds on any lane of the wave (the same answer on every lane).
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
 // Workgroup b -> tile index so that each XCD (workgroups are dealt round-robin over the
 // 8 XCDs) owns one contiguous run of tiles and its L2 sees neighbouring rays.
@@ -77,8 +79,12 @@ struct RaySeg {
 __device__ inline RaySeg ray_segment(const svr_camera& c, int px, int py, int nx, int ny,
                                      int nz, float dtf) {
 #pragma clang fp contract(off)
+    // a miss keeps n = 0 and a valid point: lanes without samples still run the (uniform)
+    // march loop and fetch at the volume origin
     RaySeg r;
     r.n = 0;
+    r.p0[0] = r.p0[1] = r.p0[2] = 0.0f;
+    r.step[0] = r.step[1] = r.step[2] = 0.0f;
     const double u = 2.0 * ((double)px + 0.5) / (double)c.width - 1.0;
     const double v = 2.0 * ((double)py + 0.5) / (double)c.height - 1.0;
     double o[3], d[3];

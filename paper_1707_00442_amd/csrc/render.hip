@@ -5,8 +5,9 @@
 // tiles are dealt to XCDs in contiguous runs.  Ray setup is FP64 (once per ray); the hot
 // loop is FP32: a trilinear fetch from the bricked, aproned volume (eight loads sharing one
 // address), the filter, the transfer function and compositing.  The colour table and the
-// per-lane box-smoothing ring live in LDS.  A wave leaves the loop when all its lanes are
-// done (AVIP early termination is per lane; the wave retires with its last ray).
+// per-lane box-smoothing ring live in LDS.  The sample loop is uniform across the wave, with
+// the loads of two further samples in flight while a sample is blended; the wave leaves it
+// once none of its rays needs another sample (AVIP early termination is per ray).
 #include "march.h"
 
 namespace svr {
@@ -24,15 +25,17 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int px = tx * kTile + (w & 1) * 8 + (l & 7);
     const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
-    if (px >= a.cam.width || py >= a.cam.height) return;
+    const bool inside = px < a.cam.width && py < a.cam.height;
 
     float4 res;
     int count;
     float* ring = reinterpret_cast<float*>(smem + n_lut) + threadIdx.x;
-    render_ray<MODE, RATIO, DT, C>(a, s_lut, ring, px, py, res, count);
-    const size_t pix = (size_t)py * a.cam.width + px;
-    a.out[pix] = res;
-    if (a.samples) a.samples[pix] = count;
+    render_ray<MODE, RATIO, DT, C>(a, s_lut, ring, px, py, inside, res, count);
+    if (inside) {
+        const size_t pix = (size_t)py * a.cam.width + px;
+        a.out[pix] = res;
+        if (a.samples) a.samples[pix] = count;
+    }
 }
 
 using RenderFn = void (*)(RenderArgs);

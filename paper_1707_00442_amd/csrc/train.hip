@@ -43,10 +43,10 @@ __device__ __forceinline__ void avip_step(AvipState& t, float4 c, float kw, floa
     const float a2 = kw * c.w * (1.0f - a1);
     const float al = fmaxf(a1 + a2, minv);
     const float ri = rcp(al);
-    const float w1 = a1 * ri, w2 = a2 * ri;
-    t.r = fmaf(t.r, w1, c.x * w2);
-    t.g = fmaf(t.g, w1, c.y * w2);
-    t.b = fmaf(t.b, w1, c.z * w2);
+    const float w2 = a2 * ri, wd = (al - a1) * ri;  // c + (c_s a2 - c (al - a1)) / al
+    t.r = fmaf(c.x, w2, fmaf(-t.r, wd, t.r));
+    t.g = fmaf(c.y, w2, fmaf(-t.g, wd, t.g));
+    t.b = fmaf(c.z, w2, fmaf(-t.b, wd, t.b));
     t.a = al;
 }
 
@@ -152,10 +152,10 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
                 const bool active = sum >= minv;
                 const float al = fmaxf(sum, minv);
                 const float ri = rcp(al);
-                const float w1 = a1 * ri, w2 = a2 * ri;
-                const float C1r = fmaf(S0.x, w1, c.x * w2);
-                const float C1g = fmaf(S0.y, w1, c.y * w2);
-                const float C1b = fmaf(S0.z, w1, c.z * w2);
+                const float w1 = a1 * ri, w2 = a2 * ri, wd = (al - a1) * ri;
+                const float C1r = fmaf(c.x, w2, fmaf(-S0.x, wd, S0.x));  // as avip_step
+                const float C1g = fmaf(c.y, w2, fmaf(-S0.y, wd, S0.y));
+                const float C1b = fmaf(c.z, w2, fmaf(-S0.z, wd, S0.z));
                 const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
                 const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (active ? g_al : 0.0f);
                 const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri +
