@@ -42,14 +42,14 @@ __global__ void batch_reset_kernel(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
 }
 
-template <int MODE, int DT, int C>
+template <int MODE, int DT, int C, bool WIDE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
     extern __shared__ float4 smem[];
     __shared__ int s_item;
     float4* s_lut = smem;
     const int n_lut = b.lut_n;
-    for (int i = threadIdx.x; i < n_lut; i += kBlock) s_lut[i] = b.lut[i];
-    float* ring = reinterpret_cast<float*>(smem + n_lut) + threadIdx.x;
+    stage_table(s_lut, b.lut, n_lut);
+    float* ring = reinterpret_cast<float*>(smem + n_lut + 1) + threadIdx.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int tw = b.tw, th = 4 / tw;
     const int wx = w % tw, wy = w / tw;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
             a.nblocks = 0;
             float4 res;
             int count;
-            render_ray<MODE, 0, DT, C>(a, s_lut, ring, px, py, inside, res, count);
+            render_ray<MODE, 0, DT, C, WIDE>(a, s_lut, ring, px, py, inside, res, count);
             if (inside) bv.out[(size_t)py * bv.cam.width + px] = res;
         }
     }
@@ -87,27 +87,33 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
 
 using BatchFn = void (*)(BatchArgs);
 
-template <int DT, int C>
+template <int DT, int C, bool WIDE>
 static BatchFn batch_pick(int mode) {
     switch (mode) {
-        case SVR_MIP0: return batch_kernel<SVR_MIP0, DT, C>;
-        case SVR_MIP1: return batch_kernel<SVR_MIP1, DT, C>;
-        case SVR_MIPRGB: return batch_kernel<SVR_MIPRGB, DT, C>;
-        case SVR_AVIP0: return batch_kernel<SVR_AVIP0, DT, C>;
-        case SVR_AVIP1: return batch_kernel<SVR_AVIP1, DT, C>;
-        default: return batch_kernel<SVR_AVIPRGB, DT, C>;
+        case SVR_MIP0: return batch_kernel<SVR_MIP0, DT, C, WIDE>;
+        case SVR_MIP1: return batch_kernel<SVR_MIP1, DT, C, WIDE>;
+        case SVR_MIPRGB: return batch_kernel<SVR_MIPRGB, DT, C, WIDE>;
+        case SVR_AVIP0: return batch_kernel<SVR_AVIP0, DT, C, WIDE>;
+        case SVR_AVIP1: return batch_kernel<SVR_AVIP1, DT, C, WIDE>;
+        default: return batch_kernel<SVR_AVIPRGB, DT, C, WIDE>;
     }
 }
 
-static BatchFn batch_pick_any(int dtype, int brick, int mode) {
+template <bool WIDE>
+static BatchFn batch_pick_dt(int dtype, int brick, int mode) {
     if (brick == 16) {
-        if (dtype == SVR_F16) return batch_pick<SVR_F16, 16>(mode);
-        if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 16>(mode);
-        return batch_pick<SVR_F32, 16>(mode);
+        if (dtype == SVR_F16) return batch_pick<SVR_F16, 16, WIDE>(mode);
+        if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 16, WIDE>(mode);
+        return batch_pick<SVR_F32, 16, WIDE>(mode);
     }
-    if (dtype == SVR_F16) return batch_pick<SVR_F16, 8>(mode);
-    if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 8>(mode);
-    return batch_pick<SVR_F32, 8>(mode);
+    if (dtype == SVR_F16) return batch_pick<SVR_F16, 8, WIDE>(mode);
+    if (dtype == SVR_BF16) return batch_pick<SVR_BF16, 8, WIDE>(mode);
+    return batch_pick<SVR_F32, 8, WIDE>(mode);
+}
+
+static BatchFn batch_pick_any(int dtype, int brick, bool wide, int mode) {
+    return wide ? batch_pick_dt<true>(dtype, brick, mode)
+                : batch_pick_dt<false>(dtype, brick, mode);
 }
 
 // Host estimate of the samples a tile costs: the longest chord among its four corner rays
@@ -297,7 +303,9 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
     b->args.lut = reinterpret_cast<const float4*>(lut->rgba);
     b->args.lut_n = lut->n;
     b->args.p = *params;
-    b->fn = batch_pick_any(b->dtype, b->brick, b->mode);
+    bool wide = false;
+    for (int i = 0; i < n; ++i) wide = wide || wide_volume(vols[i]->d);
+    b->fn = batch_pick_any(b->dtype, b->brick, wide, b->mode);
     b->lds = render_lds_bytes(lut->n, params->box_arm, 0);
     hipError_t e = hipMalloc(&b->d_counter, 64);
     if (e != hipSuccess) {

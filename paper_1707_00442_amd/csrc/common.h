@@ -127,18 +127,59 @@ __device__ inline RaySeg ray_segment(const svr_camera& c, int px, int py, int nx
     return r;
 }
 
-// Table lookup: n RGBA entries at j/(n-1), linear interpolation; s in [0, 1].
-__device__ __forceinline__ float4 table(const float4* L, int n, float s) {
-    const float x = s * (float)(n - 1);
-    int j = (int)x;
-    j = j > n - 2 ? n - 2 : j;
-    const float f = x - (float)j;
+// One step of the normalised front-to-back compositing of Alg. AVIP0 (Eq. for alpha_2 and
+// the colour/alpha update): a2 = k op (1 - a1), al = max(a1 + a2, minVal), colour
+// c a1/al + c_s a2/al.  The colour update is evaluated as c + (c_s a2 - c (al - a1))/al,
+// the same value in exact arithmetic, which leaves c exactly unchanged where a sample adds
+// no opacity (a2 = 0, al = a1); the plain form would multiply c by a rounded a1 (1/al)
+// ~ 1 +- 1 ulp on each such sample.  An inactive step (active = false) adds no opacity and
+// keeps alpha, so it changes nothing.  Contraction is off so that every caller rounds
+// a1 + a2 the same way.  Returns the new alpha.
+struct Rgba {
+    float r, g, b, a;
+};
+
+__device__ __forceinline__ float composite(Rgba& t, float cr, float cg, float cb, float op,
+                                           float kw, float minv, bool active) {
+#pragma clang fp contract(off)
+    const float a1 = t.a;
+    const float a2 = active ? kw * op * (1.0f - a1) : 0.0f;
+    const float al0 = fmaxf(a1 + a2, minv);  // >= minv > 0
+    const float al = active ? al0 : a1;
+    const float ri = rcp(al0);
+    const float w2 = a2 * ri, wd = (al - a1) * ri;
+    t.r = fmaf(cr, w2, fmaf(-t.r, wd, t.r));
+    t.g = fmaf(cg, w2, fmaf(-t.g, wd, t.g));
+    t.b = fmaf(cb, w2, fmaf(-t.b, wd, t.b));
+    t.a = al;
+    return al;
+}
+
+// Colour/opacity table in LDS: the n entries followed by a copy of the last one, so the
+// lookup needs no index clamp.
+__device__ __forceinline__ void stage_table(float4* dst, const float4* src, int n) {
+    for (int i = (int)threadIdx.x; i <= n; i += (int)blockDim.x) dst[i] = src[i < n ? i : n - 1];
+}
+
+// Table lookup: n RGBA entries at j/(n-1), linear interpolation; s in [0, 1], nm1 = n - 1.
+// x = s (n-1) lies in [0, n-1]: interval j = trunc(x), weight f = x - j (exact).  At s = 1
+// this reads entry n-1 with weight 1 - 0 and its copy with weight 0.
+__device__ __forceinline__ float4 table(const float4* L, float nm1, float s) {
+    const float x = s * nm1;
+    const uint32_t j = (uint32_t)x;
+    const float f = __builtin_amdgcn_fractf(x);
     const float4 a = L[j], b = L[j + 1];
     return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y),
                        fmaf(f, b.z - a.z, a.z), fmaf(f, b.w - a.w, a.w));
 }
 
 // Host side helpers --------------------------------------------------------------------
+// True when a volume's bricked storage spans more than 2^32 bytes (64-bit addressing).
+inline bool wide_volume(const VolDesc& d) {
+    const uint64_t esize = d.dtype == SVR_F32 ? 4 : 2;
+    return (uint64_t)d.nbx * d.nby * d.nbz * d.pitch * esize > 0xffffffffull;
+}
+
 void set_error(const char* fmt, ...);
 svr_status hip_fail(hipError_t e, const char* what);
 

@@ -80,14 +80,14 @@ __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, in
           });
 }
 
-template <int MODE, int RATIO, int DT, int C, bool BOX>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, bool BOX>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
-    using Smp = Sampler<DT, C>;
+    using Smp = Sampler<DT, C, WIDE>;
     const Smp smp(a.v);
     const int N = r.n;
-    const int n_lut = a.lut_n;
+    const float n_lut = (float)(a.lut_n - 1);
     res = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     count = N;
 
@@ -174,7 +174,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     const float kw = a.p.k, minv = a.p.min_val, ert = a.p.ert;
     const bool ofl = a.p.opacity_from_lut != 0;
     const float inx = 1.0f / (float)a.v.nx, iny = 1.0f / (float)a.v.ny, inz = 1.0f / (float)a.v.nz;
-    float tr = 0.0f, tg = 0.0f, tb = 0.0f, ta = 0.0f;
+    Rgba t = {0.0f, 0.0f, 0.0f, 0.0f};
     int cnt = 0;
     for_each_value<BOX>(smp, r, a.p.box_arm, ring, [&](int k, float v, bool active) -> bool {
         const float s = F(v);
@@ -196,29 +196,17 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
             }
             op = ofl ? table(s_lut, n_lut, s).w : s;
         }
-        // The colour update c a1/al + c_s a2/al is evaluated as c + (c_s a2 - c (al - a1))/al,
-        // the same value in exact arithmetic.  This form leaves c exactly unchanged where a
-        // sample adds no opacity (a2 = 0, al = a1), so long transparent stretches after the
-        // first opaque sample do not multiply c by a rounded a1 (1/al) ~ 1 +- 1 ulp each step.
-        const float a1 = ta;
-        const float a2 = kw * op * (1.0f - a1);
-        const float al = fmaxf(a1 + a2, minv);
-        const float ri = rcp(al);
-        const float w2 = a2 * ri, wd = (al - a1) * ri;
-        tr = active ? fmaf(cr, w2, fmaf(-tr, wd, tr)) : tr;
-        tg = active ? fmaf(cg, w2, fmaf(-tg, wd, tg)) : tg;
-        tb = active ? fmaf(cb, w2, fmaf(-tb, wd, tb)) : tb;
-        ta = active ? al : ta;
+        const float al = composite(t, cr, cg, cb, op, kw, minv, active);
         cnt += active ? 1 : 0;
         return active && !(al > ert);
     });
     count = cnt;
-    if (N > 0) res = make_float4(tr, tg, tb, ta);
+    if (N > 0) res = make_float4(t.r, t.g, t.b, t.a);
 }
 
 // One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
 // is uniform); lanes outside the image pass inside = false and march no samples.
-template <int MODE, int RATIO, int DT, int C>
+template <int MODE, int RATIO, int DT, int C, bool WIDE>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
@@ -250,9 +238,9 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_
         r.step[0] = r.step[1] = r.step[2] = 0.0f;
     }
     if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, true>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, true>(a, s_lut, ring, r, F, res, count);
     else
-        march<MODE, RATIO, DT, C, false>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, false>(a, s_lut, ring, r, F, res, count);
 }
 
 size_t render_lds_bytes(int lut_n, int box_arm, int ratio);

@@ -12,12 +12,12 @@
 
 namespace svr {
 
-template <int MODE, int RATIO, int DT, int C>
+template <int MODE, int RATIO, int DT, int C, bool WIDE>
 __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     extern __shared__ float4 smem[];
     float4* s_lut = smem;
     const int n_lut = a.lut_n;
-    for (int i = threadIdx.x; i < n_lut; i += kBlock) s_lut[i] = a.lut[i];
+    stage_table(s_lut, a.lut, n_lut);
     __syncthreads();
 
     const int t = xcd_tile((int)blockIdx.x, a.nblocks);
@@ -29,8 +29,8 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
 
     float4 res;
     int count;
-    float* ring = reinterpret_cast<float*>(smem + n_lut) + threadIdx.x;
-    render_ray<MODE, RATIO, DT, C>(a, s_lut, ring, px, py, inside, res, count);
+    float* ring = reinterpret_cast<float*>(smem + n_lut + 1) + threadIdx.x;
+    render_ray<MODE, RATIO, DT, C, WIDE>(a, s_lut, ring, px, py, inside, res, count);
     if (inside) {
         const size_t pix = (size_t)py * a.cam.width + px;
         a.out[pix] = res;
@@ -40,33 +40,39 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
 
 using RenderFn = void (*)(RenderArgs);
 
-template <int DT, int C>
+template <int DT, int C, bool WIDE>
 static RenderFn pick(int mode, int ratio) {
-    if (ratio == 1) return render_kernel<SVR_MIP0, 1, DT, C>;
-    if (ratio == 2) return render_kernel<SVR_MIP0, 2, DT, C>;
+    if (ratio == 1) return render_kernel<SVR_MIP0, 1, DT, C, WIDE>;
+    if (ratio == 2) return render_kernel<SVR_MIP0, 2, DT, C, WIDE>;
     switch (mode) {
-        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C>;
-        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C>;
-        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C>;
-        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C>;
-        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C>;
-        default: return render_kernel<SVR_AVIPRGB, 0, DT, C>;
+        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C, WIDE>;
+        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C, WIDE>;
+        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C, WIDE>;
+        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C, WIDE>;
+        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C, WIDE>;
+        default: return render_kernel<SVR_AVIPRGB, 0, DT, C, WIDE>;
     }
 }
 
-static RenderFn pick_any(int dtype, int brick, int mode, int ratio) {
+template <bool WIDE>
+static RenderFn pick_dt(int dtype, int brick, int mode, int ratio) {
     if (brick == 16) {
-        if (dtype == SVR_F16) return pick<SVR_F16, 16>(mode, ratio);
-        if (dtype == SVR_BF16) return pick<SVR_BF16, 16>(mode, ratio);
-        return pick<SVR_F32, 16>(mode, ratio);
+        if (dtype == SVR_F16) return pick<SVR_F16, 16, WIDE>(mode, ratio);
+        if (dtype == SVR_BF16) return pick<SVR_BF16, 16, WIDE>(mode, ratio);
+        return pick<SVR_F32, 16, WIDE>(mode, ratio);
     }
-    if (dtype == SVR_F16) return pick<SVR_F16, 8>(mode, ratio);
-    if (dtype == SVR_BF16) return pick<SVR_BF16, 8>(mode, ratio);
-    return pick<SVR_F32, 8>(mode, ratio);
+    if (dtype == SVR_F16) return pick<SVR_F16, 8, WIDE>(mode, ratio);
+    if (dtype == SVR_BF16) return pick<SVR_BF16, 8, WIDE>(mode, ratio);
+    return pick<SVR_F32, 8, WIDE>(mode, ratio);
+}
+
+static RenderFn pick_any(int dtype, int brick, bool wide, int mode, int ratio) {
+    return wide ? pick_dt<true>(dtype, brick, mode, ratio)
+                : pick_dt<false>(dtype, brick, mode, ratio);
 }
 
 size_t render_lds_bytes(int lut_n, int box_arm, int ratio) {
-    size_t b = (size_t)lut_n * sizeof(float4);
+    size_t b = (size_t)(lut_n + 1) * sizeof(float4);
     if (ratio == 0 && box_arm > 0) b += (size_t)(2 * box_arm + 1) * kBlock * sizeof(float);
     return b;
 }
@@ -86,7 +92,8 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
     a.tiles_x = (cam.width + kTile - 1) / kTile;
     const int tiles_y = (cam.height + kTile - 1) / kTile;
     a.nblocks = a.tiles_x * tiles_y;
-    RenderFn fn = pick_any(v->d.dtype, v->d.brick, p.mode, p.ratio);
+    const bool wide = wide_volume(v->d) || (v2 != nullptr && wide_volume(v2->d));
+    RenderFn fn = pick_any(v->d.dtype, v->d.brick, wide, p.mode, p.ratio);
     const size_t lds = render_lds_bytes(lut.n, p.box_arm, p.ratio);
     hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(kBlock), lds, stream, a);
     return hip_fail(hipGetLastError(), "render launch");

@@ -11,11 +11,15 @@ namespace svr {
 // local offset, and the eight corners are read at compile-time offsets from one address
 // (the apron holds the +1 neighbours, so no corner leaves the brick and the upper edge
 // needs no index clamp).  Interpolation order x, then y, then z, each a + f (b - a).
-template <int DT, int C>
+//
+// WIDE = false addresses the storage with 32-bit byte offsets from a scalar base (volumes
+// below 4 GiB); WIDE = true forms 64-bit addresses.
+template <int DT, int C, bool WIDE>
 struct Sampler {
     using T = typename Elem<DT>::T;
     static constexpr int E = C + 1;
     static constexpr int SH = C == 8 ? 3 : 4;
+    static constexpr uint32_t kM24 = 0xffffffu;
     const T* data;
     float xm, ym, zm;
     uint32_t nbx, nby, pitch;
@@ -26,30 +30,44 @@ struct Sampler {
         float fx, fy, fz;
     };
 
+    // Brick counts and the pitch are below 2^24 (checked at volume creation); the masks
+    // let the compiler use 24-bit multiplies.
     __device__ __forceinline__ explicit Sampler(const VolDesc& v)
         : data(static_cast<const T*>(v.data)),
           xm((float)(v.nx - 1)), ym((float)(v.ny - 1)), zm((float)(v.nz - 1)),
-          nbx((uint32_t)v.nbx), nby((uint32_t)v.nby), pitch(v.pitch) {}
+          nbx((uint32_t)v.nbx & kM24), nby((uint32_t)v.nby & kM24), pitch(v.pitch & kM24) {}
 
-    // Element offset of voxel cell (ix, iy, iz) inside the bricked storage.  Brick counts,
-    // the brick pitch and their product stay below 2^24 x 2^13 < 2^32 (checked at volume
-    // creation), so 24-bit multiplies are exact.
+    // Element offset of voxel cell (ix, iy, iz) inside the bricked storage: brick index
+    // (below 2^24) times the pitch plus the in-brick offset, below 2^32 in total.
     __device__ __forceinline__ uint32_t offset(uint32_t ix, uint32_t iy, uint32_t iz) const {
-        const uint32_t b = __umul24(__umul24(iz >> SH, nby) + (iy >> SH), nbx) + (ix >> SH);
+        __builtin_assume(ix <= kM24);
+        __builtin_assume(iy <= kM24);
+        __builtin_assume(iz <= kM24);
+        uint32_t b = (iz >> SH) * nby + (iy >> SH);
+        __builtin_assume(b <= kM24);
+        b = b * nbx + (ix >> SH);
+        __builtin_assume(b <= kM24);
         const uint32_t loc = ((iz & (C - 1)) * E + (iy & (C - 1))) * E + (ix & (C - 1));
-        return __umul24(b, pitch) + loc;
+        return b * pitch + loc;
     }
 
+    __device__ __forceinline__ const T* at(uint32_t off) const {
+        if (WIDE) return data + off;
+        return reinterpret_cast<const T*>(reinterpret_cast<const char*>(data) +
+                                          off * (uint32_t)sizeof(T));
+    }
+
+    // The point is clamped to [0, n-1], so the cell index is its truncation and the
+    // fraction point - floor(point) is exact (v_fract).
     __device__ __forceinline__ Fetch fetch(float x, float y, float z) const {
         x = med3(x, 0.0f, xm);
         y = med3(y, 0.0f, ym);
         z = med3(z, 0.0f, zm);
-        const float x0 = floorf(x), y0 = floorf(y), z0 = floorf(z);
         Fetch f;
-        f.fx = x - x0;
-        f.fy = y - y0;
-        f.fz = z - z0;
-        const T* q = data + offset((uint32_t)x0, (uint32_t)y0, (uint32_t)z0);
+        f.fx = __builtin_amdgcn_fractf(x);
+        f.fy = __builtin_amdgcn_fractf(y);
+        f.fz = __builtin_amdgcn_fractf(z);
+        const T* q = at(offset((uint32_t)x, (uint32_t)y, (uint32_t)z));
         f.c000 = Elem<DT>::get(q, 0);
         f.c100 = Elem<DT>::get(q, 1);
         f.c010 = Elem<DT>::get(q, E);

@@ -33,27 +33,17 @@ struct TrainArgs {
     float* grad_vox;
 };
 
-// One step of the normalised front-to-back compositing of Alg. AVIP0, as in the render path.
-struct AvipState {
-    float r, g, b, a;
-};
+// One step of the compositing of Alg. AVIP0, the same function as the render path.
+using AvipState = Rgba;
 
 __device__ __forceinline__ void avip_step(AvipState& t, float4 c, float kw, float minv) {
-    const float a1 = t.a;
-    const float a2 = kw * c.w * (1.0f - a1);
-    const float al = fmaxf(a1 + a2, minv);
-    const float ri = rcp(al);
-    const float w2 = a2 * ri, wd = (al - a1) * ri;  // c + (c_s a2 - c (al - a1)) / al
-    t.r = fmaf(c.x, w2, fmaf(-t.r, wd, t.r));
-    t.g = fmaf(c.y, w2, fmaf(-t.g, wd, t.g));
-    t.b = fmaf(c.z, w2, fmaf(-t.b, wd, t.b));
-    t.a = al;
+    composite(t, c.x, c.y, c.z, c.w, kw, minv, true);
 }
 
 template <int DT, int C>
 __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
-    __shared__ float4 s_tf[kTrainMaxTf];
-    for (int i = threadIdx.x; i < a.tf_n; i += kBlock) s_tf[i] = a.tf[i];
+    __shared__ float4 s_tf[kTrainMaxTf + 1];
+    stage_table(s_tf, a.tf, a.tf_n);
     __syncthreads();
     const int t = xcd_tile((int)blockIdx.x, a.nblocks);
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
@@ -72,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
     }
     const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
     const RaySeg r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
-    const Sampler<DT, C> smp(a.v);
+    const Sampler<DT, C, true> smp(a.v);
     AvipState st{0.0f, 0.0f, 0.0f, 0.0f};
     const float kw = a.p.k, minv = a.p.min_val, ert = a.p.ert;
     int K = 0;
@@ -83,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
         const float v = smp(fmaf(kf, r.step[0], r.p0[0]), fmaf(kf, r.step[1], r.p0[1]),
                             fmaf(kf, r.step[2], r.p0[2]));
         const float s = __saturatef((v - lo) * inv);
-        avip_step(st, table(s_tf, a.tf_n, s), kw, minv);
+        avip_step(st, table(s_tf, (float)(a.tf_n - 1), s), kw, minv);
         ++K;
         if (st.a > ert) break;
     }
@@ -93,13 +83,13 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
 
 template <int DT, int C>
 __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
-    __shared__ float4 s_tf[kTrainMaxTf];
+    __shared__ float4 s_tf[kTrainMaxTf + 1];
     __shared__ float s_gtf[kTrainMaxTf * 4];
     __shared__ float4 s_state[kCkptEvery][kWave];
     __shared__ float s_s[kCkptEvery][kWave];
     const int n = a.tf_n;
     const int l = threadIdx.x;
-    for (int i = l; i < n; i += kWave) s_tf[i] = a.tf[i];
+    stage_table(s_tf, a.tf, n);
     for (int i = l; i < 4 * n; i += kWave) s_gtf[i] = 0.0f;
     __syncthreads();
 
@@ -118,7 +108,7 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
         }
         const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
         const RaySeg r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
-        const Sampler<DT, C> smp(a.v);
+        const Sampler<DT, C, true> smp(a.v);
         const float kw = a.p.k, minv = a.p.min_val;
         const float nm1 = (float)(n - 1);
         const float4 g = a.grad[(size_t)py * a.cam.width + px];
@@ -138,17 +128,17 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
                 const float s = __saturatef((v - lo) * inv);
                 s_state[k - k0][l] = make_float4(st.r, st.g, st.b, st.a);
                 s_s[k - k0][l] = s;
-                avip_step(st, table(s_tf, n, s), kw, minv);
+                avip_step(st, table(s_tf, nm1, s), kw, minv);
             }
             // reverse recurrence
             for (int k = k1 - 1; k >= k0; --k) {
                 const float4 S0 = s_state[k - k0][l];
                 const float s = s_s[k - k0][l];
-                const float4 c = table(s_tf, n, s);
+                const float4 c = table(s_tf, nm1, s);
                 const float a_ = kw * c.w;
                 const float a1 = S0.w;
                 const float a2 = a_ * (1.0f - a1);
-                const float sum = a1 + a2;
+                const float sum = __fadd_rn(a1, a2);  // rounded as in composite()
                 const bool active = sum >= minv;
                 const float al = fmaxf(sum, minv);
                 const float ri = rcp(al);
