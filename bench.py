@@ -428,10 +428,13 @@ def _make_sub(spec):
 
 
 def run_batched(torch, svr, synth, lut):
+    import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
     specs = synth.subcube_batch_specs(512, 0)
     t = time.time()
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+    # fresh worker processes (numpy only): no fork of this GPU-initialised process
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4), mp_context=ctx) as ex:
         cubes = list(ex.map(_make_sub, specs, chunksize=8))
     log(f"  generated 512 sub-cubes in {time.time() - t:.1f}s")
     vols, cams = [], []

@@ -62,8 +62,10 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
         const int2 item = b.items[it];
         const BatchVol& bv = b.vols[item.x];
         const int tx = item.y % bv.tiles_x, ty = item.y / bv.tiles_x;
-        const int px = tx * (8 * tw) + wx * 8 + (l & 7);
-        const int py = ty * (8 * th) + wy * 8 + (l >> 3);
+        int lx, ly;
+        wave_pixel<DT>(l, lx, ly);
+        const int px = tx * (8 * tw) + wx * 8 + lx;
+        const int py = ty * (8 * th) + wy * 8 + ly;
         const bool inside = px < bv.cam.width && py < bv.cam.height;
         {
             RenderArgs a;

@@ -69,8 +69,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // Ray of one pixel and its entry into the box [-0.5, n-0.5]^3, in double precision with
 // every operation rounded separately (no contraction), so the entry point and the sample
 // count match an IEEE double evaluation of the same formulas.  Returns the sample count
-// (0 on a miss) and the first sample position / per-sample step rounded to float.
+// (0 on a miss), the first sample position q0 and the per-sample step dq in double (sample
+// k sits at q0 + k dq; positions reach ~1e3 voxels, where float spacing is ~1e-4 voxel,
+// too coarse for trilinear weights near steep gradients), and both rounded to float for
+// the normalised locations loc = (p + 0.5)/n that only colour the result.
 struct RaySeg {
+    double q0[3];
+    double dq[3];
     float p0[3];
     float step[3];
     int32_t n;
@@ -83,6 +88,8 @@ __device__ inline RaySeg ray_segment(const svr_camera& c, int px, int py, int nx
     // march loop and fetch at the volume origin
     RaySeg r;
     r.n = 0;
+    r.q0[0] = r.q0[1] = r.q0[2] = 0.0;
+    r.dq[0] = r.dq[1] = r.dq[2] = 0.0;
     r.p0[0] = r.p0[1] = r.p0[2] = 0.0f;
     r.step[0] = r.step[1] = r.step[2] = 0.0f;
     const double u = 2.0 * ((double)px + 0.5) / (double)c.width - 1.0;
@@ -121,8 +128,10 @@ __device__ inline RaySeg ray_segment(const svr_camera& c, int px, int py, int nx
     const double dt = (double)dtf;
     r.n = (int32_t)ceil((tf - tn) / dt);
     for (int a = 0; a < 3; ++a) {
-        r.p0[a] = (float)(o[a] + tn * d[a]);
-        r.step[a] = (float)(dt * d[a]);
+        r.q0[a] = o[a] + tn * d[a];
+        r.dq[a] = dt * d[a];
+        r.p0[a] = (float)r.q0[a];
+        r.step[a] = (float)r.dq[a];
     }
     return r;
 }

@@ -234,6 +234,8 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_
         r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
     } else {
         r.n = 0;
+        r.q0[0] = r.q0[1] = r.q0[2] = 0.0;
+        r.dq[0] = r.dq[1] = r.dq[2] = 0.0;
         r.p0[0] = r.p0[1] = r.p0[2] = 0.0f;
         r.step[0] = r.step[1] = r.step[2] = 0.0f;
     }
@@ -241,6 +243,21 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_
         march<MODE, RATIO, DT, C, WIDE, true>(a, s_lut, ring, r, F, res, count);
     else
         march<MODE, RATIO, DT, C, WIDE, false>(a, s_lut, ring, r, F, res, count);
+}
+
+// Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works
+// on quarter-waves of 16 lanes and its cost grows with the distinct cache lines each quarter
+// touches; for 4-byte voxels a 4x4 pixel block per quarter (Z order) touches fewer lines
+// than an 8x2 strip, for 2-byte voxels (rows of half the length) the strip is cheaper.
+template <int DT>
+__device__ __forceinline__ void wave_pixel(int l, int& lx, int& ly) {
+    if (DT == SVR_F32) {
+        lx = (l & 1) | ((l >> 1) & 2) | ((l >> 2) & 4);
+        ly = ((l >> 1) & 1) | ((l >> 2) & 2) | ((l >> 3) & 4);
+    } else {
+        lx = l & 7;
+        ly = l >> 3;
+    }
 }
 
 size_t render_lds_bytes(int lut_n, int box_arm, int ratio);

@@ -23,8 +23,10 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     const int t = xcd_tile((int)blockIdx.x, a.nblocks);
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int px = tx * kTile + (w & 1) * 8 + (l & 7);
-    const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+    int lx, ly;
+    wave_pixel<DT>(l, lx, ly);
+    const int px = tx * kTile + (w & 1) * 8 + lx;
+    const int py = ty * kTile + (w >> 1) * 8 + ly;
     const bool inside = px < a.cam.width && py < a.cam.height;
 
     float4 res;

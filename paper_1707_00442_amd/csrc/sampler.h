@@ -21,7 +21,7 @@ struct Sampler {
     static constexpr int SH = C == 8 ? 3 : 4;
     static constexpr uint32_t kM24 = 0xffffffu;
     const T* data;
-    float xm, ym, zm;
+    double xm, ym, zm;
     uint32_t nbx, nby, pitch;
 
     // Loads in flight for one sample: its eight corners and the cell fractions.
@@ -34,7 +34,7 @@ struct Sampler {
     // let the compiler use 24-bit multiplies.
     __device__ __forceinline__ explicit Sampler(const VolDesc& v)
         : data(static_cast<const T*>(v.data)),
-          xm((float)(v.nx - 1)), ym((float)(v.ny - 1)), zm((float)(v.nz - 1)),
+          xm((double)(v.nx - 1)), ym((double)(v.ny - 1)), zm((double)(v.nz - 1)),
           nbx((uint32_t)v.nbx & kM24), nby((uint32_t)v.nby & kM24), pitch(v.pitch & kM24) {}
 
     // Element offset of voxel cell (ix, iy, iz) inside the bricked storage: brick index
@@ -57,16 +57,16 @@ struct Sampler {
                                           off * (uint32_t)sizeof(T));
     }
 
-    // The point is clamped to [0, n-1], so the cell index is its truncation and the
-    // fraction point - floor(point) is exact (v_fract).
-    __device__ __forceinline__ Fetch fetch(float x, float y, float z) const {
-        x = med3(x, 0.0f, xm);
-        y = med3(y, 0.0f, ym);
-        z = med3(z, 0.0f, zm);
+    // The point (double) is clamped to [0, n-1], so the cell index is its truncation; the
+    // fraction point - floor(point) is exact in double (v_fract) and then rounded to float.
+    __device__ __forceinline__ Fetch fetch(double x, double y, double z) const {
+        x = fmin(fmax(x, 0.0), xm);
+        y = fmin(fmax(y, 0.0), ym);
+        z = fmin(fmax(z, 0.0), zm);
         Fetch f;
-        f.fx = __builtin_amdgcn_fractf(x);
-        f.fy = __builtin_amdgcn_fractf(y);
-        f.fz = __builtin_amdgcn_fractf(z);
+        f.fx = (float)__builtin_amdgcn_fract(x);
+        f.fy = (float)__builtin_amdgcn_fract(y);
+        f.fz = (float)__builtin_amdgcn_fract(z);
         const T* q = at(offset((uint32_t)x, (uint32_t)y, (uint32_t)z));
         f.c000 = Elem<DT>::get(q, 0);
         f.c100 = Elem<DT>::get(q, 1);
@@ -89,23 +89,29 @@ struct Sampler {
         return fmaf(f.fz, b1 - b0, b0);
     }
 
-    __device__ __forceinline__ float operator()(float x, float y, float z) const {
+    __device__ __forceinline__ float operator()(double x, double y, double z) const {
         return blend(fetch(x, y, z));
     }
 };
 
-// Samples along one ray: value j is the sample at p0 + (j + base) step.
+// Samples along one ray, fetched in order: fetch number j (j = 0, 1, 2, ...) is the sample
+// at q0 + (j + base) dq.  The position is advanced in double by one step per fetch; the
+// accumulated rounding stays below 1e-9 voxel for any realistic ray length.
 template <class S>
 struct RaySource {
     using Fetch = typename S::Fetch;
     const S& smp;
-    float p0x, p0y, p0z, sx, sy, sz, base;
-    __device__ __forceinline__ RaySource(const S& s, const RaySeg& r, float base_)
-        : smp(s), p0x(r.p0[0]), p0y(r.p0[1]), p0z(r.p0[2]), sx(r.step[0]), sy(r.step[1]),
-          sz(r.step[2]), base(base_) {}
-    __device__ __forceinline__ Fetch fetch(float j) const {
-        const float kf = j + base;
-        return smp.fetch(fmaf(kf, sx, p0x), fmaf(kf, sy, p0y), fmaf(kf, sz, p0z));
+    double px, py, pz, dqx, dqy, dqz;
+    __device__ __forceinline__ RaySource(const S& s, const RaySeg& r, float base)
+        : smp(s), px(fma((double)base, r.dq[0], r.q0[0])),
+          py(fma((double)base, r.dq[1], r.q0[1])), pz(fma((double)base, r.dq[2], r.q0[2])),
+          dqx(r.dq[0]), dqy(r.dq[1]), dqz(r.dq[2]) {}
+    __device__ __forceinline__ Fetch next() {
+        const Fetch f = smp.fetch(px, py, pz);
+        px += dqx;
+        py += dqy;
+        pz += dqz;
+        return f;
     }
     static __device__ __forceinline__ float value(const Fetch& f) { return S::blend(f); }
 };
@@ -119,7 +125,7 @@ struct PairSource {
     RaySource<S> ra, rb;
     __device__ __forceinline__ PairSource(const S& s1, const S& s2, const RaySeg& r)
         : ra(s1, r, 0.0f), rb(s2, r, 0.0f) {}
-    __device__ __forceinline__ Fetch fetch(float j) const { return Fetch{ra.fetch(j), rb.fetch(j)}; }
+    __device__ __forceinline__ Fetch next() { return Fetch{ra.next(), rb.next()}; }
     static __device__ __forceinline__ float2 value(const Fetch& f) {
         return make_float2(S::blend(f.a), S::blend(f.b));
     }
@@ -133,18 +139,17 @@ struct PairSource {
 // once no lane needs a further sample.  Fetches of inactive lanes read clamped points
 // inside the volume and are never used.
 template <class Src, class Body>
-__device__ __forceinline__ void drive(const Src& src, int n, Body&& body) {
+__device__ __forceinline__ void drive(Src src, int n, Body&& body) {
     if (!wave_any(n > 0)) return;
-    typename Src::Fetch q0 = src.fetch(0.0f);
-    typename Src::Fetch q1 = src.fetch(1.0f);
+    typename Src::Fetch q0 = src.next();
+    typename Src::Fetch q1 = src.next();
     bool alive = true;
-    float jf = 0.0f;
-    for (int j = 0;; j += 3, jf += 3.0f) {
-        typename Src::Fetch q2 = src.fetch(jf + 2.0f);
+    for (int j = 0;; j += 3) {
+        typename Src::Fetch q2 = src.next();
         alive = body(j, Src::value(q0), alive && j < n);
-        q0 = src.fetch(jf + 3.0f);
+        q0 = src.next();
         alive = body(j + 1, Src::value(q1), alive && j + 1 < n);
-        q1 = src.fetch(jf + 4.0f);
+        q1 = src.next();
         alive = body(j + 2, Src::value(q2), alive && j + 2 < n);
         if (!wave_any(alive && j + 3 < n)) break;
     }

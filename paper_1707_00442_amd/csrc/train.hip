@@ -70,8 +70,9 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
     for (int k = 0; k < r.n; ++k, kf += 1.0f) {
         if ((k & (kCkptEvery - 1)) == 0)
             a.ckpt[(int64_t)(k / kCkptEvery) * a.nrays + rid] = make_float4(st.r, st.g, st.b, st.a);
-        const float v = smp(fmaf(kf, r.step[0], r.p0[0]), fmaf(kf, r.step[1], r.p0[1]),
-                            fmaf(kf, r.step[2], r.p0[2]));
+        const double kd = (double)kf;
+        const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
+                            fma(kd, r.dq[2], r.q0[2]));
         const float s = __saturatef((v - lo) * inv);
         avip_step(st, table(s_tf, (float)(a.tf_n - 1), s), kw, minv);
         ++K;
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
         const float4 g = a.grad[(size_t)py * a.cam.width + px];
         float gr = g.x, gg = g.y, gb = g.z, ga = g.w;
         const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
-        const float xm = (float)(a.v.nx - 1), ym = (float)(a.v.ny - 1), zm = (float)(a.v.nz - 1);
+        const double xm = a.v.nx - 1, ym = a.v.ny - 1, zm = a.v.nz - 1;
         for (int seg = (K - 1) / kCkptEvery; seg >= 0; --seg) {
             const int k0 = seg * kCkptEvery;
             const int k1 = min(k0 + kCkptEvery, K);
@@ -122,9 +123,9 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
             AvipState st{c0.x, c0.y, c0.z, c0.w};
             // replay the segment, keeping the state before each sample
             for (int k = k0; k < k1; ++k) {
-                const float kf = (float)k;
-                const float v = smp(fmaf(kf, r.step[0], r.p0[0]), fmaf(kf, r.step[1], r.p0[1]),
-                                    fmaf(kf, r.step[2], r.p0[2]));
+                const double kd = (double)k;
+                const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
+                                    fma(kd, r.dq[2], r.q0[2]));
                 const float s = __saturatef((v - lo) * inv);
                 s_state[k - k0][l] = make_float4(st.r, st.g, st.b, st.a);
                 s_s[k - k0][l] = s;
@@ -170,13 +171,15 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
                     const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
                                       gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
                     const float gv = gs * inv;
-                    const float kf = (float)k;
-                    const float px_ = med3(fmaf(kf, r.step[0], r.p0[0]), 0.0f, xm);
-                    const float py_ = med3(fmaf(kf, r.step[1], r.p0[1]), 0.0f, ym);
-                    const float pz_ = med3(fmaf(kf, r.step[2], r.p0[2]), 0.0f, zm);
-                    const float x0 = floorf(px_), y0 = floorf(py_), z0 = floorf(pz_);
-                    const float fx = px_ - x0, fy = py_ - y0, fz = pz_ - z0;
-                    const uint32_t i0 = (uint32_t)x0, j0 = (uint32_t)y0, l0 = (uint32_t)z0;
+                    // the cell and fractions of the forward fetch (double positions)
+                    const double kd = (double)k;
+                    const double px_ = fmin(fmax(fma(kd, r.dq[0], r.q0[0]), 0.0), xm);
+                    const double py_ = fmin(fmax(fma(kd, r.dq[1], r.q0[1]), 0.0), ym);
+                    const double pz_ = fmin(fmax(fma(kd, r.dq[2], r.q0[2]), 0.0), zm);
+                    const float fx = (float)__builtin_amdgcn_fract(px_);
+                    const float fy = (float)__builtin_amdgcn_fract(py_);
+                    const float fz = (float)__builtin_amdgcn_fract(pz_);
+                    const uint32_t i0 = (uint32_t)px_, j0 = (uint32_t)py_, l0 = (uint32_t)pz_;
                     const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1);
                     const uint32_t l1 = min(l0 + 1, nz - 1);
                     const size_t r00 = ((size_t)l0 * ny + j0) * nx, r10 = ((size_t)l0 * ny + j1) * nx;

@@ -1,0 +1,246 @@
+"""GPU parity at the full benchmark sizes, in the launch configurations bench.py times.
+
+The 512 x 512 x 1024 float32 HI-like cube (noise + 50 rotating discs, seed 0) is rendered
+whole at 1920 x 1080 from rotation views (dt = 0.5, clipping at minT = 3, k = 0.22); the
+oracle then renders a random sample of those pixels one by one and every sampled pixel is
+compared.  Also at full size: the six transfer functions, float16/bfloat16 storage, the
+low-density parallel view, the in-ray line ratios over the two 32-channel windows, the
+voxel-wise line-ratio pass, the three smoothing passes (sampled voxels against the direct
+triple sum) and the batched launch of the 512 sub-cubes (sampled pixels of sampled cubes).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import quant
+from helpers import COND_TOL, TOL16, TOL32, compare_render, margins, oracle_render, to_cuda
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = 512, 512, 1024
+W, H = 1920, 1080
+NPIX = 3000
+MODES = ["mip0", "mip1", "miprgb", "avip0", "avip1", "aviprgb"]
+
+
+@pytest.fixture(scope="module")
+def svr():
+    import paper_1707_00442_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def full(svr):
+    print("[full] building the 512x512x1024 cube", flush=True)
+    cube = synth.cfg1_cube(0)
+    t = to_cuda(cube)
+    lo, hi = svr.svr_minmax(t)
+    rlo, rhi = quant.finite_minmax(cube)
+    assert (lo, hi) == (float(np.float32(rlo)), float(np.float32(rhi)))
+    vol = svr.svr_volume_create(t)
+    views = [v.as_f32() for v in synth.rotation_views(NX, NY, NZ, W, H)]
+    yield dict(cube=cube, t=t, lo=lo, hi=hi, vol=vol, views=views)
+    vol.close()
+
+
+def _sample_pixels(ns_full, n, seed):
+    """n random pixels, half of them among the pixels whose ray hits the cube."""
+    rng = np.random.default_rng(seed)
+    hit = np.nonzero(ns_full > 0)[0]
+    a = rng.choice(hit, n // 2, replace=False)
+    b = rng.choice(ns_full.size, n - n // 2, replace=False)
+    return np.unique(np.concatenate([a, b]))
+
+
+def _render_sampled(svr, vol, cam, lut_np, params, lo, hi, seed, vol2=None):
+    img, ns = svr.svr_render(vol, cam, to_cuda(lut_np), params, clim_lo=lo, clim_hi=hi,
+                             vol2=vol2, samples=True)
+    svr.svr_sync()
+    img = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    ns = ns.cpu().numpy().ravel()
+    pix = _sample_pixels(ns, NPIX, seed)
+    return img[pix], ns[pix], pix
+
+
+@pytest.mark.parametrize("view", [3, 12, 21])
+@pytest.mark.parametrize("mode", MODES)
+def test_full_frame_transfer_functions(svr, full, mode, view):
+    cam = full["views"][view]
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, k=0.22, filter="clip", min_t=3.0)
+    lo, hi = full["lo"], full["hi"]
+    print(f"[full] {mode} view {view}", flush=True)
+    got, ns, pix = _render_sampled(svr, full["vol"], cam, lut, params, lo, hi, seed=view)
+    err, frag, nert = compare_render(oracle, got, ns, full["cube"], cam, lut, params, lo, hi,
+                                     pixels=pix, margins=margins(lo, hi, params),
+                                     cond_tol=COND_TOL)
+    hit = int((ns > 0).sum())
+    print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit (termination re-checked "
+          f"{nert}), samples {int(ns.sum())}", flush=True)
+    assert err <= TOL32
+    assert frag.sum() < 0.05 * hit
+    assert hit > NPIX // 3
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("mode", ["mip0", "avip0"])
+def test_full_frame_half_storage(svr, full, storage, mode):
+    """16-bit storage at full size: <= 1e-5 against the oracle on the stored values; against
+    the float32 cube the error is the storage rounding carried through the transfer
+    function (mean <= 2e-3; max within 2e-3 or the rounding bound times the table slope)."""
+    cube = full["cube"]
+    deq = quant.dequantize(cube, storage)
+    lo, hi = quant.finite_minmax(deq)
+    lo, hi = float(np.float32(lo)), float(np.float32(hi))
+    cam = full["views"][7]
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, k=0.22, filter="clip", min_t=3.0)
+    vol = svr.svr_volume_create(full["t"], storage=storage)
+    got, ns, pix = _render_sampled(svr, vol, cam, lut, params, lo, hi, seed=40)
+    vol.close()
+    e1, frag, _ = compare_render(oracle, got, ns, deq, cam, lut, params, lo, hi, pixels=pix,
+                                 margins=margins(lo, hi, params))
+    ref32, frag32, _ = oracle_render(oracle, cube, cam, lut, params, lo, hi, pixels=pix,
+                                     margins=margins(lo, hi, params))
+    ok = ~(frag | (frag32 != 0))
+    d = np.abs(got - ref32)[ok]
+    vmax = float(np.abs(cube).max())
+    ulp_top = 2.0 ** (np.floor(np.log2(vmax)) - (10 if storage == "f16" else 7))
+    slope = float(np.abs(np.diff(lut, axis=0)).max() * (lut.shape[0] - 1))
+    qbound = 0.5 * ulp_top / (hi - lo) * max(slope, 1.0)
+    print(f"[full {storage}/{mode}] vs stored {e1:.3e}; vs float32 cube max {d.max():.3e} "
+          f"mean {d.mean():.3e} (rounding bound x slope {qbound:.3e}); fragile "
+          f"{frag.sum()}", flush=True)
+    assert e1 <= TOL32
+    assert d.mean() <= TOL16
+    assert d.max() <= max(TOL16, 1.05 * qbound)
+
+
+def test_full_sparse_parallel_view(svr, full):
+    """The low-density view (parallel along +z, 256 x 256 over the 512 x 512 face, dt = 1):
+    every pixel against the oracle."""
+    cam = synth.ortho_axis(NX, NY, NZ, 256, 256, "+z").as_f32()
+    lut = synth.lut_heat(256)
+    params = dict(mode="mip0", k=0.22, filter="clip", min_t=3.0, dt=1.0)
+    lo, hi = full["lo"], full["hi"]
+    img, ns = svr.svr_render(full["vol"], cam, to_cuda(lut), params, clim_lo=lo, clim_hi=hi,
+                             samples=True)
+    svr.svr_sync()
+    got = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    ns = ns.cpu().numpy().ravel()
+    assert (ns == NZ).all()
+    err, frag, _ = compare_render(oracle, got, ns, full["cube"], cam, lut, params, lo, hi,
+                                  margins=margins(lo, hi, params))
+    print(f"[full sparse] max err {err:.3e} fragile {frag.sum()}", flush=True)
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_full_ratio_windows(svr, full, method):
+    """In-ray line ratios over the spectral windows [400, 432) and [600, 632) of the full
+    cube (both clipped at 3), at a rotation view of the 512 x 512 x 32 windows."""
+    cube = full["cube"]
+    wa, wb = np.ascontiguousarray(cube[400:432]), np.ascontiguousarray(cube[600:632])
+    va, vb = svr.svr_volume_create(to_cuda(wa)), svr.svr_volume_create(to_cuda(wb))
+    rlo, rhi = svr.svr_volume_clim(va)
+    cam = synth.rotation_views(NX, NY, 32, W, H)[5].as_f32()
+    lut = synth.lut_heat(256)
+    params = dict(mode="mip0", ratio=method, filter="clip", min_t=3.0, min_t2=3.0,
+                  ratio_lo=0.0, ratio_hi=2.0)
+    got, ns, pix = _render_sampled(svr, va, cam, lut, params, rlo, rhi, seed=50 + method,
+                                   vol2=vb)
+    err, frag, _ = compare_render(oracle, got, ns, wa, cam, lut, params, rlo, rhi, cube2=wb,
+                                  pixels=pix, margins=margins(rlo, rhi, params))
+    hit = int((ns > 0).sum())
+    print(f"[full ratio m{method}] max err {err:.3e} fragile {frag.sum()} / {hit}", flush=True)
+    va.close()
+    vb.close()
+    assert err <= TOL32
+    assert hit - frag.sum() >= NPIX // 4
+
+
+def test_full_line_ratio_pass(svr, full):
+    """The voxel-wise ratio cube of the two windows, clipped at 3, DATAMIN = lo: every
+    voxel within one float32 rounding of the FP64 ratio."""
+    out = svr.svr_line_ratio(full["t"], 400, 600, 32, min_t_a=3.0, min_t_b=3.0,
+                             datamin=full["lo"])
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.line_ratio(full["cube"], 400, 600, 32, 3.0, 3.0, datamin=full["lo"])
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
+    print(f"[full line ratio] max rel err {rel.max():.3e}", flush=True)
+    assert rel.max() <= 2.0 ** -24 * 1.01
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 3])
+def test_full_smoothing_sampled_voxels(svr, full, sigma):
+    """The separable Gaussian pass at sigma = 1, 2, 3 voxels on the full cube against the
+    direct triple sum at sampled voxels (interior, faces, edges and corners)."""
+    from paper_1707_00442_amd import taps as tapgen
+    g = tapgen.gauss(float(sigma)).astype(np.float32)
+    out = svr.svr_smooth(full["t"], g)
+    rng = np.random.default_rng(sigma)
+    zs = np.concatenate([rng.integers(0, NZ, 300), [0, NZ - 1, 0, NZ - 1, 5, NZ - 3]])
+    ys = np.concatenate([rng.integers(0, NY, 300), [0, NY - 1, NY - 1, 0, 0, 2]])
+    xs = np.concatenate([rng.integers(0, NX, 300), [0, NX - 1, 0, NX - 1, NX - 1, 1]])
+    got = out[zs, ys, xs].cpu().numpy().astype(np.float64)
+    idx = (zs.astype(np.int64) * NY + ys) * NX + xs
+    ref = oracle.smooth_at(full["cube"], g.astype(np.float64), idx)
+    bound = 3 * len(g) * 2.0 ** -24 * np.abs(g).sum() ** 3 * np.abs(full["cube"]).max()
+    err = np.abs(got - ref)
+    print(f"[full smooth sigma {sigma}] max err {err.max():.3e} (bound {bound:.3e})",
+          flush=True)
+    assert np.all(err <= bound)
+
+
+def test_full_upload_round_trip(svr, full):
+    """Upload into the bricked volume (the timed step re-bricks the cube in place) and
+    export: the float32 cube comes back bit for bit."""
+    svr.svr_volume_upload(full["vol"], full["t"])
+    back = svr.svr_volume_export(full["vol"])
+    import torch
+    assert torch.equal(back, full["t"])
+
+
+def test_full_batched_sub_cubes(svr):
+    """The 512 float16 sub-cubes (sizes log-uniform in [32, 256] x [32, 256] x [64, 512])
+    at 512 x 512 each in one autotuned persistent launch: sampled pixels of sampled cubes
+    against the oracle on the stored values."""
+    specs = synth.subcube_batch_specs(512, 0)
+    lut_np = synth.lut_heat(256)
+    lut = to_cuda(lut_np)
+    pick = set(np.random.default_rng(9).choice(512, 6, replace=False).tolist())
+    vols, cams, kept = [], [], {}
+    for i, sp in enumerate(specs):
+        c = synth.subcube(sp)
+        vols.append(svr.svr_volume_create(to_cuda(c), storage="f16"))
+        v = sp["view"] / np.linalg.norm(sp["view"])
+        radius = 0.5 * np.sqrt(sp["nx"] ** 2 + sp["ny"] ** 2 + sp["nz"] ** 2)
+        centre = ((sp["nx"] - 1) / 2, (sp["ny"] - 1) / 2, (sp["nz"] - 1) / 2)
+        cams.append(synth.perspective_direction(centre, v, 2 * radius, 30.0, 512,
+                                                512).as_f32())
+        if i in pick:
+            kept[i] = c.astype(np.float32)
+        if (i + 1) % 128 == 0:
+            print(f"[full batch] {i + 1} sub-cubes uploaded", flush=True)
+    for mode in ("mip0", "avip0"):
+        p = dict(mode=mode, k=0.22)
+        b = svr.svr_batch_create(vols, cams, lut, p, tune=True)
+        b.launch()
+        svr.svr_sync()
+        for i in sorted(pick):
+            lo, hi = svr.svr_volume_clim(vols[i])
+            img = b.outs[i].cpu().numpy().reshape(-1, 4).astype(np.float64)
+            _, ns = svr.svr_render(vols[i], cams[i], lut, p, samples=True)
+            ns = ns.cpu().numpy().ravel()
+            pix = _sample_pixels(ns, 1000, seed=i)
+            err, frag, _ = compare_render(oracle, img[pix], ns[pix], kept[i], cams[i], lut_np,
+                                          p, lo, hi, pixels=pix,
+                                          margins=margins(lo, hi, p))
+            print(f"  {mode} cube {i} {specs[i]['nx']}x{specs[i]['ny']}x{specs[i]['nz']}: "
+                  f"max err {err:.3e} fragile {frag.sum()}", flush=True)
+            assert err <= TOL32
+        b.close()
+    for v in vols:
+        v.close()

@@ -14,38 +14,10 @@ import pytest
 import oracle
 import synth
 from oracle import quant
-from helpers import (assert_counts, compare_render, f32, gpu_render, max_err,
-                     oracle_render, to_cuda)
+from helpers import (AMP_MAX, COND_TOL, TOL16, TOL32, assert_counts, compare_render, f32,  # noqa: F401,E501
+                     gpu_render, margins, max_err, oracle_render, to_cuda)
 
 pytestmark = pytest.mark.gpu
-
-TOL32 = 1e-5
-TOL16 = 2e-3
-
-
-AMP_MAX = 6.0
-# Ill-conditioned pixels (amplification above AMP_MAX) still carry only rounding-level
-# errors; this bound catches a wrong colour or weight on them.
-COND_TOL = 1e-3
-
-
-def margins(lo, hi, params=None, **kw):
-    """Decision margins sized to the float32 path's errors (sample values within about
-    1.2e-6 of the value range on average, up to ~1e-5 at steep gradients far from the
-    origin): thresholds dv, ties ds, termination da.  The conditioning
-    probe moves every sample by pv = 1e-7 of the range and flags pixels whose RGBA moves by
-    more than AMP_MAX times the resulting change of s (a direct map through a table moves
-    by its slope, <= 3); s moves by pv/(hi - lo), or pv/(max_t - min_t) under domain
-    scaling.  Sample errors of the float32 path reach ~1.3e-6 in s, so amplification 6
-    keeps robust pixels under the 1e-5 tolerance."""
-    pv = 1e-7 * (hi - lo)
-    slope = 1.0 / (hi - lo)
-    if params and params.get("filter") == "scale":
-        slope = 1.0 / (params["max_t"] - params["min_t"])
-    m = dict(dv=1e-5 * (hi - lo), ds=1e-5, da=2e-6, pv=pv, pt=AMP_MAX * pv * slope)
-    m.update(kw)
-    return m
-
 
 @pytest.fixture(scope="module")
 def svr():
