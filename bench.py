@@ -50,12 +50,26 @@ PEAK_ALU = 256 * 64 * 2.4e9  # VALU lane operations/s (256 CUs x 4 SIMD x 16 lan
 OPS_PER_SAMPLE = {"mip0": 31, "mip1": 33, "miprgb": 33, "avip0": 56, "avip1": 58,
                   "aviprgb": 48, "ratio1": 26 * 2 + 6 + 2, "ratio2": 26 * 2 + 6 + 4}
 MODES = ("mip0", "mip1", "miprgb", "avip0", "avip1", "aviprgb")
-KERNEL_SOURCES = ("common.h", "sampler.h", "march.h", "render.hip")
+# sources of each kernel family (recorded counters are void once any of them changes)
+KERNEL_SOURCES = {
+    "render": ("common.h", "sampler.h", "march.h", "render.hip"),
+    "smooth": ("common.h", "smooth.hip"),
+    "line_ratio": ("common.h", "smooth.hip"),
+    "upload": ("common.h", "volume.hip"),
+    "copy": (),
+}
 
 
-def source_hash(names=KERNEL_SOURCES):
+def kernel_family(kernel):
+    for fam in ("render", "smooth", "line_ratio", "upload", "copy"):
+        if kernel.startswith(fam):
+            return fam
+    raise KeyError(kernel)
+
+
+def source_hash(kernel):
     h = hashlib.sha256()
-    for n in names:
+    for n in KERNEL_SOURCES[kernel_family(kernel)]:
         with open(os.path.join(ROOT, "paper_1707_00442_amd", "csrc", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -119,7 +133,7 @@ def load_traffic(kernel):
     try:
         d = json.load(open(path))
         e = d.get(kernel)
-        if e and e.get("source_hash") == source_hash():
+        if e and e.get("source_hash") == source_hash(kernel):
             return e.get("bytes_per_launch")
     except Exception:
         return None
@@ -297,8 +311,11 @@ def sparse_camera(synth):
 
 def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, smooth_out, ws,
                 ratio_out, lo):
+    """Run one kernel --steps times on the views the timed loop renders (after --warmup),
+    so per-launch counters compare with the timed per-launch figures."""
     name = args.profile
-    cam = views[0]
+    cams = [views[(args.warmup + i) % len(views)] for i in range(args.steps)]
+    it = iter(range(args.steps))
     if name == "copy":
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -309,7 +326,7 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
         fn = lambda: svr.svr_render(vol, c, lut, p)  # noqa: E731
     elif name.startswith("render_"):
         m = name[len("render_"):]
-        fn = lambda: svr.svr_render(vol, cam, lut, params[m])  # noqa: E731
+        fn = lambda: svr.svr_render(vol, cams[next(it)], lut, params[m])  # noqa: E731
     elif name.startswith("smooth_sigma"):
         s = int(name[-1])
         fn = lambda: svr.svr_smooth(cube, taps[s], out=smooth_out, workspace=ws)  # noqa: E731
@@ -323,7 +340,7 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
         fn()
         torch.cuda.synchronize()
         log(f"profile {name}: call {i + 1}/{args.steps} done")
-    print(json.dumps({"profiled": name, "calls": args.steps, "source_hash": source_hash()}))
+    print(json.dumps({"profiled": name, "calls": args.steps, "source_hash": source_hash(name)}))
 
 
 class _Null:
