@@ -372,7 +372,8 @@ def test_line_ratio_pass(svr, dtype):
 
 
 # ----------------------------------------------------------------------------- smoothing
-@pytest.mark.parametrize("taps_name", ["binomial5", "paper9", "binomial13", "gauss1", "gauss3"])
+@pytest.mark.parametrize("taps_name", ["binomial3", "binomial5", "paper9", "binomial13", "gauss1",
+                                       "gauss3", "gauss4"])
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_smooth_parity(svr, taps_name, dtype):
     """Separable smoothing vs the oracle (float64), ragged dims: error within the float32
@@ -380,8 +381,10 @@ def test_smooth_parity(svr, taps_name, dtype):
     plus that bound (16-bit output)."""
     from oracle import taps as T
     import torch
-    g = {"binomial5": T.binomial(5), "paper9": T.paper9(), "binomial13": T.binomial(13),
-         "gauss1": T.gauss(1.0), "gauss3": T.gauss(3.0)}[taps_name]
+    # 5, 7, 9, 13 and 19 taps run the fixed-size kernels, 3 and 25 the generic ones
+    g = {"binomial3": T.binomial(3), "binomial5": T.binomial(5), "paper9": T.paper9(),
+         "binomial13": T.binomial(13), "gauss1": T.gauss(1.0), "gauss3": T.gauss(3.0),
+         "gauss4": T.gauss(4.0)}[taps_name]
     g32 = g.astype(np.float32)
     cube = synth.blob_cube(41, 3, seed=6)[:, :29, :37].copy()
     store = quant.dequantize(cube, dtype)
