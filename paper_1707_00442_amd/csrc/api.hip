@@ -30,9 +30,9 @@ svr_status hip_fail(hipError_t e, const char* what) {
 size_t minmax_partial_floats();
 svr_status launch_minmax(const svr_cube_view& c, float* partial, float* out, int raw,
                          int out_dtype, float nan_fill, hipStream_t stream);
-svr_status launch_brick(const svr_cube_view& c, const VolDesc& d, const float* aux,
-                        hipStream_t stream);
 svr_status launch_export(const VolDesc& d, void* out, hipStream_t stream);
+svr_status launch_upload(const svr_cube_view& c, const VolDesc& d, float* aux, float nan_fill,
+                         hipStream_t stream);
 svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_camera& cam,
                          const svr_lut& lut, const svr_params& p, float* out,
                          int32_t* samples, hipStream_t stream);
@@ -203,8 +203,7 @@ svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t 
     d.data = v->mem;
     d.clim = v->aux;
     v->d = d;
-    st = launch_minmax(*src, v->aux + 4, v->aux, 0, storage, nan_fill, S(stream));
-    if (!st) st = launch_brick(*src, v->d, v->aux, S(stream));
+    st = launch_upload(*src, v->d, v->aux, nan_fill, S(stream));
     if (st) {
         (void)hipFree(v->mem);
         (void)hipFree(v->aux);
@@ -224,9 +223,7 @@ svr_status svr_volume_upload(svr_volume* vol, const svr_cube_view* src, float na
               "svr_volume_upload: dims %d x %d x %d differ from the volume's", src->nx, src->ny,
               src->nz);
     SVR_CHECK(!isinf(nan_fill), "nan_fill must be finite or NaN");
-    st = launch_minmax(*src, vol->aux + 4, vol->aux, 0, vol->d.dtype, nan_fill, S(stream));
-    if (st) return st;
-    return launch_brick(*src, vol->d, vol->aux, S(stream));
+    return launch_upload(*src, vol->d, vol->aux, nan_fill, S(stream));
 }
 
 svr_status svr_volume_destroy(svr_volume* vol) {

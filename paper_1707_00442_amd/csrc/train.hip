@@ -5,12 +5,8 @@
 // is stored, and at the end the number of composited samples K.  The image equals the
 // plain render with opacity_from_lut = 1.
 //
-// Backward (train_bwd_kernel): one wave per 8x8 pixel tile.  Each ray walks its segments
-// from the last to the first: it reloads the segment's stored state, replays the segment
-// forward keeping the per-sample state and s in LDS (32 x 20 bytes per lane), then runs the
-// reverse recurrence of the normalised compositing step.  Transfer-function gradients are
-// reduced in LDS per workgroup and flushed with one global atomic per entry; voxel
-// gradients go to the eight trilinear corners with hardware float atomics.
+// Backward (train_bwd_kernel): see the kernel.  Per-sample states live in registers for one
+// 8-sample sub-segment at a time (two-level replay from the 32-sample checkpoints).
 #include "sampler.h"
 
 namespace svr {
@@ -82,23 +78,76 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
     a.out[(size_t)py * a.cam.width + px] = make_float4(st.r, st.g, st.b, st.a);
 }
 
+// Per-lane accumulators flushed only when their key changes: consecutive samples of a ray
+// usually share the table interval and the voxel cell, so most atomic adds are merged.
+struct TfAccum {
+    int j = -1;
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ __forceinline__ void flush(float* s_gtf) {
+        if (j < 0) return;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (v[q] != 0.0f) atomicAdd(&s_gtf[4 * j + q], v[q]);
+    }
+    __device__ __forceinline__ void add(float* s_gtf, int jj, const float (&e)[8]) {
+        if (jj != j) {
+            flush(s_gtf);
+            j = jj;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = e[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] += e[q];
+        }
+    }
+};
+
+struct VoxAccum {
+    int64_t key = -1;  // linear index of the cell's first corner
+    uint32_t i0 = 0, j0 = 0, l0 = 0;
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
+        if (key < 0) return;
+        const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
+        const size_t r00 = ((size_t)l0 * ny + j0) * nx, r10 = ((size_t)l0 * ny + j1) * nx;
+        const size_t r01 = ((size_t)l1 * ny + j0) * nx, r11 = ((size_t)l1 * ny + j1) * nx;
+        unsafeAtomicAdd(G + r00 + i0, v[0]);
+        unsafeAtomicAdd(G + r00 + i1, v[1]);
+        unsafeAtomicAdd(G + r10 + i0, v[2]);
+        unsafeAtomicAdd(G + r10 + i1, v[3]);
+        unsafeAtomicAdd(G + r01 + i0, v[4]);
+        unsafeAtomicAdd(G + r01 + i1, v[5]);
+        unsafeAtomicAdd(G + r11 + i0, v[6]);
+        unsafeAtomicAdd(G + r11 + i1, v[7]);
+    }
+};
+
+constexpr int kSub = 4;  // samples per sub-segment (held in registers)
+static_assert(kCkptEvery % kSub == 0, "checkpoint segments split into sub-segments");
+
+// Backward: the workgroup layout and ray ids of the forward pass.  Each ray walks its
+// checkpoint segments from the last to the first.  A segment is replayed once from its
+// stored state to find the states at its sub-segment starts; each sub-segment, last first,
+// is replayed again into registers (state before each sample and its s) and then run
+// through the reverse recurrence of the normalised compositing step.  Gradients of the
+// table entries go to the workgroup's LDS copy (one global atomic per entry at the end),
+// gradients of the voxels to the eight trilinear corners with hardware float atomics.
 template <int DT, int C>
-__global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
+__global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
     __shared__ float4 s_tf[kTrainMaxTf + 1];
     __shared__ float s_gtf[kTrainMaxTf * 4];
-    __shared__ float4 s_state[kCkptEvery][kWave];
-    __shared__ float s_s[kCkptEvery][kWave];
+    __shared__ float4 s_sub[kCkptEvery / kSub][kBlock];  // sub-segment start states
     const int n = a.tf_n;
-    const int l = threadIdx.x;
     stage_table(s_tf, a.tf, n);
-    for (int i = l; i < 4 * n; i += kWave) s_gtf[i] = 0.0f;
+    for (int i = threadIdx.x; i < 4 * n; i += kBlock) s_gtf[i] = 0.0f;
     __syncthreads();
 
-    const int t = (int)blockIdx.x >> 2, sub = (int)blockIdx.x & 3;
+    const int t = xcd_tile((int)blockIdx.x, a.nblocks);
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
-    const int px = tx * kTile + (sub & 1) * 8 + (l & 7);
-    const int py = ty * kTile + (sub >> 1) * 8 + (l >> 3);
-    const int64_t rid = (int64_t)t * kBlock + sub * kWave + l;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int px = tx * kTile + (w & 1) * 8 + (l & 7);
+    const int py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+    const int64_t rid = (int64_t)t * kBlock + threadIdx.x;
     const bool inside = px < a.cam.width && py < a.cam.height;
     const int K = inside ? a.kcount[rid] : 0;
     if (K > 0) {
@@ -116,96 +165,121 @@ __global__ __launch_bounds__(kWave) void train_bwd_kernel(const TrainArgs a) {
         float gr = g.x, gg = g.y, gb = g.z, ga = g.w;
         const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
         const double xm = a.v.nx - 1, ym = a.v.ny - 1, zm = a.v.nz - 1;
+        TfAccum tfa;
+        VoxAccum vxa;
+        // normalised value of sample k (the forward pass's fetch, filter none)
+        auto sample_s = [&](int k) -> float {
+            const double kd = (double)k;
+            const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
+                                fma(kd, r.dq[2], r.q0[2]));
+            return __saturatef((v - lo) * inv);
+        };
+        // reverse step for sample k with state-before S0 and value s
+        auto reverse = [&](int k, const float4 S0, float s) {
+            const float4 c = table(s_tf, nm1, s);
+            const float a_ = kw * c.w;
+            const float a1 = S0.w;
+            const float a2 = a_ * (1.0f - a1);
+            const float sum = __fadd_rn(a1, a2);  // rounded as in composite()
+            const bool act = sum >= minv;
+            const float al = fmaxf(sum, minv);
+            const float ri = rcp(al);
+            const float w1 = a1 * ri, w2 = a2 * ri, wd = (al - a1) * ri;
+            const float C1r = fmaf(c.x, w2, fmaf(-S0.x, wd, S0.x));  // as composite()
+            const float C1g = fmaf(c.y, w2, fmaf(-S0.y, wd, S0.y));
+            const float C1b = fmaf(c.z, w2, fmaf(-S0.z, wd, S0.z));
+            const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
+            const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (act ? g_al : 0.0f);
+            const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri + (act ? g_al : 0.0f) -
+                               g_a2 * a_;
+            const float gcr = gr * w2, gcg = gg * w2, gcb = gb * w2;
+            const float gop = kw * g_a2 * (1.0f - a1);
+            // table: interval j and weight f of the forward lookup (the entry weights)
+            const float x = s * nm1;
+            int j = (int)x;
+            j = j > n - 2 ? n - 2 : j;
+            const float f = x - (float)j;
+            const float e[8] = {(1.0f - f) * gcr, (1.0f - f) * gcg, (1.0f - f) * gcb,
+                                (1.0f - f) * gop, f * gcr, f * gcg, f * gcb, f * gop};
+            tfa.add(s_gtf, j, e);
+            if (a.grad_vox != nullptr && s > 0.0f && s < 1.0f) {
+                const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
+                const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
+                                  gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
+                const float gv = gs * inv;
+                // the cell and fractions of the forward fetch (double positions)
+                const double kd = (double)k;
+                const double px_ = fmin(fmax(fma(kd, r.dq[0], r.q0[0]), 0.0), xm);
+                const double py_ = fmin(fmax(fma(kd, r.dq[1], r.q0[1]), 0.0), ym);
+                const double pz_ = fmin(fmax(fma(kd, r.dq[2], r.q0[2]), 0.0), zm);
+                const float fx = (float)__builtin_amdgcn_fract(px_);
+                const float fy = (float)__builtin_amdgcn_fract(py_);
+                const float fz = (float)__builtin_amdgcn_fract(pz_);
+                const uint32_t i0 = (uint32_t)px_, j0 = (uint32_t)py_, l0 = (uint32_t)pz_;
+                const int64_t key = ((int64_t)l0 * ny + j0) * nx + i0;
+                const float gx0 = gv * (1.0f - fx), gx1 = gv * fx;
+                const float wy0z0 = (1.0f - fy) * (1.0f - fz), wy1z0 = fy * (1.0f - fz);
+                const float wy0z1 = (1.0f - fy) * fz, wy1z1 = fy * fz;
+                const float d8[8] = {gx0 * wy0z0, gx1 * wy0z0, gx0 * wy1z0, gx1 * wy1z0,
+                                     gx0 * wy0z1, gx1 * wy0z1, gx0 * wy1z1, gx1 * wy1z1};
+                if (key != vxa.key) {
+                    vxa.flush(a.grad_vox, nx, ny, nz);
+                    vxa.key = key;
+                    vxa.i0 = i0;
+                    vxa.j0 = j0;
+                    vxa.l0 = l0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) vxa.v[q] = d8[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) vxa.v[q] += d8[q];
+                }
+            }
+            gr *= w1;
+            gg *= w1;
+            gb *= w1;
+            ga = g_a1;
+        };
+        // one sub-segment, last sample first: replay into registers, then reverse
+        auto sub_segment = [&](int kb, int k1, Rgba st) {
+            float4 S[kSub];
+            float sv[kSub];
+#pragma unroll
+            for (int i = 0; i < kSub; ++i) {
+                S[i] = make_float4(st.r, st.g, st.b, st.a);
+                sv[i] = 0.0f;
+                if (kb + i < k1) {
+                    sv[i] = sample_s(kb + i);
+                    avip_step(st, table(s_tf, nm1, sv[i]), kw, minv);
+                }
+            }
+#pragma unroll
+            for (int i = kSub - 1; i >= 0; --i)
+                if (kb + i < k1) reverse(kb + i, S[i], sv[i]);
+        };
         for (int seg = (K - 1) / kCkptEvery; seg >= 0; --seg) {
             const int k0 = seg * kCkptEvery;
             const int k1 = min(k0 + kCkptEvery, K);
             const float4 c0 = a.ckpt[(int64_t)seg * a.nrays + rid];
-            AvipState st{c0.x, c0.y, c0.z, c0.w};
-            // replay the segment, keeping the state before each sample
-            for (int k = k0; k < k1; ++k) {
-                const double kd = (double)k;
-                const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
-                                    fma(kd, r.dq[2], r.q0[2]));
-                const float s = __saturatef((v - lo) * inv);
-                s_state[k - k0][l] = make_float4(st.r, st.g, st.b, st.a);
-                s_s[k - k0][l] = s;
-                avip_step(st, table(s_tf, nm1, s), kw, minv);
+            // states at the sub-segment starts (LDS, one slot per lane)
+            Rgba st{c0.x, c0.y, c0.z, c0.w};
+            const int nsub = (k1 - k0 + kSub - 1) / kSub;
+            for (int u = 0; u < nsub; ++u) {
+                s_sub[u][threadIdx.x] = make_float4(st.r, st.g, st.b, st.a);
+                if (u == nsub - 1) break;
+                for (int k = k0 + u * kSub; k < k0 + (u + 1) * kSub; ++k)
+                    avip_step(st, table(s_tf, nm1, sample_s(k)), kw, minv);
             }
-            // reverse recurrence
-            for (int k = k1 - 1; k >= k0; --k) {
-                const float4 S0 = s_state[k - k0][l];
-                const float s = s_s[k - k0][l];
-                const float4 c = table(s_tf, nm1, s);
-                const float a_ = kw * c.w;
-                const float a1 = S0.w;
-                const float a2 = a_ * (1.0f - a1);
-                const float sum = __fadd_rn(a1, a2);  // rounded as in composite()
-                const bool active = sum >= minv;
-                const float al = fmaxf(sum, minv);
-                const float ri = rcp(al);
-                const float w1 = a1 * ri, w2 = a2 * ri, wd = (al - a1) * ri;
-                const float C1r = fmaf(c.x, w2, fmaf(-S0.x, wd, S0.x));  // as avip_step
-                const float C1g = fmaf(c.y, w2, fmaf(-S0.y, wd, S0.y));
-                const float C1b = fmaf(c.z, w2, fmaf(-S0.z, wd, S0.z));
-                const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
-                const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (active ? g_al : 0.0f);
-                const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri +
-                                   (active ? g_al : 0.0f) - g_a2 * a_;
-                const float gcr = gr * w2, gcg = gg * w2, gcb = gb * w2;
-                const float gop = kw * g_a2 * (1.0f - a1);
-                // table: interval j, weight f (as in the forward lookup)
-                const float x = s * nm1;
-                int j = (int)x;
-                j = j > n - 2 ? n - 2 : j;
-                const float f = x - (float)j;
-                const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
-                atomicAdd(&s_gtf[4 * j + 0], (1.0f - f) * gcr);
-                atomicAdd(&s_gtf[4 * j + 1], (1.0f - f) * gcg);
-                atomicAdd(&s_gtf[4 * j + 2], (1.0f - f) * gcb);
-                atomicAdd(&s_gtf[4 * j + 3], (1.0f - f) * gop);
-                atomicAdd(&s_gtf[4 * j + 4], f * gcr);
-                atomicAdd(&s_gtf[4 * j + 5], f * gcg);
-                atomicAdd(&s_gtf[4 * j + 6], f * gcb);
-                atomicAdd(&s_gtf[4 * j + 7], f * gop);
-                if (a.grad_vox != nullptr && s > 0.0f && s < 1.0f) {
-                    const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
-                                      gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
-                    const float gv = gs * inv;
-                    // the cell and fractions of the forward fetch (double positions)
-                    const double kd = (double)k;
-                    const double px_ = fmin(fmax(fma(kd, r.dq[0], r.q0[0]), 0.0), xm);
-                    const double py_ = fmin(fmax(fma(kd, r.dq[1], r.q0[1]), 0.0), ym);
-                    const double pz_ = fmin(fmax(fma(kd, r.dq[2], r.q0[2]), 0.0), zm);
-                    const float fx = (float)__builtin_amdgcn_fract(px_);
-                    const float fy = (float)__builtin_amdgcn_fract(py_);
-                    const float fz = (float)__builtin_amdgcn_fract(pz_);
-                    const uint32_t i0 = (uint32_t)px_, j0 = (uint32_t)py_, l0 = (uint32_t)pz_;
-                    const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1);
-                    const uint32_t l1 = min(l0 + 1, nz - 1);
-                    const size_t r00 = ((size_t)l0 * ny + j0) * nx, r10 = ((size_t)l0 * ny + j1) * nx;
-                    const size_t r01 = ((size_t)l1 * ny + j0) * nx, r11 = ((size_t)l1 * ny + j1) * nx;
-                    const float gx0 = gv * (1.0f - fx), gx1 = gv * fx;
-                    const float wy0z0 = (1.0f - fy) * (1.0f - fz), wy1z0 = fy * (1.0f - fz);
-                    const float wy0z1 = (1.0f - fy) * fz, wy1z1 = fy * fz;
-                    float* G = a.grad_vox;
-                    unsafeAtomicAdd(G + r00 + i0, gx0 * wy0z0);
-                    unsafeAtomicAdd(G + r00 + i1, gx1 * wy0z0);
-                    unsafeAtomicAdd(G + r10 + i0, gx0 * wy1z0);
-                    unsafeAtomicAdd(G + r10 + i1, gx1 * wy1z0);
-                    unsafeAtomicAdd(G + r01 + i0, gx0 * wy0z1);
-                    unsafeAtomicAdd(G + r01 + i1, gx1 * wy0z1);
-                    unsafeAtomicAdd(G + r11 + i0, gx0 * wy1z1);
-                    unsafeAtomicAdd(G + r11 + i1, gx1 * wy1z1);
-                }
-                gr *= w1;
-                gg *= w1;
-                gb *= w1;
-                ga = g_a1;
+            for (int u = nsub - 1; u >= 0; --u) {
+                const float4 q = s_sub[u][threadIdx.x];
+                sub_segment(k0 + u * kSub, k1, Rgba{q.x, q.y, q.z, q.w});
             }
         }
+        tfa.flush(s_gtf);
+        if (a.grad_vox != nullptr) vxa.flush(a.grad_vox, nx, ny, nz);
     }
     __syncthreads();
-    for (int i = l; i < 4 * n; i += kWave) {
+    for (int i = threadIdx.x; i < 4 * n; i += kBlock) {
         const float v = s_gtf[i];
         if (v != 0.0f) unsafeAtomicAdd(a.grad_tf + i, v);
     }
@@ -258,7 +332,7 @@ static void train_launch(bool fwd, const TrainArgs& a, hipStream_t s) {
     if (fwd)
         hipLaunchKernelGGL((train_fwd_kernel<DT, C>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((train_bwd_kernel<DT, C>), dim3(a.nblocks * 4), dim3(kWave), 0, s, a);
+        hipLaunchKernelGGL((train_bwd_kernel<DT, C>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
 }
 
 static void train_dispatch(bool fwd, int dtype, int brick, const TrainArgs& a, hipStream_t s) {
