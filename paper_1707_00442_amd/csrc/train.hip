@@ -106,19 +106,46 @@ struct VoxAccum {
     int64_t key = -1;  // linear index of the cell's first corner
     uint32_t i0 = 0, j0 = 0, l0 = 0;
     float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // Corner q of the cell is (dx, dy, dz) = (q & 1, (q >> 1) & 1, q >> 2).  Neighbouring
+    // rays share corners, so lane l issues corner (q + l) mod 8 at step q: the lanes of one
+    // atomic instruction then mostly target distinct addresses (atomics to one address
+    // within an instruction are serialised).
     __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
         if (key < 0) return;
         const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
-        const size_t r00 = ((size_t)l0 * ny + j0) * nx, r10 = ((size_t)l0 * ny + j1) * nx;
-        const size_t r01 = ((size_t)l1 * ny + j0) * nx, r11 = ((size_t)l1 * ny + j1) * nx;
-        unsafeAtomicAdd(G + r00 + i0, v[0]);
-        unsafeAtomicAdd(G + r00 + i1, v[1]);
-        unsafeAtomicAdd(G + r10 + i0, v[2]);
-        unsafeAtomicAdd(G + r10 + i1, v[3]);
-        unsafeAtomicAdd(G + r01 + i0, v[4]);
-        unsafeAtomicAdd(G + r01 + i1, v[5]);
-        unsafeAtomicAdd(G + r11 + i0, v[6]);
-        unsafeAtomicAdd(G + r11 + i1, v[7]);
+        const int64_t dxo = (int64_t)i1 - i0;
+        const int64_t dyo = ((int64_t)j1 - j0) * nx;
+        const int64_t dzo = ((int64_t)l1 - l0) * nx * ny;
+        float* base = G + key;
+        const int rot = (int)(threadIdx.x & 7);
+        // rotate (v[0..7]) left by rot with three conditional stages
+        float r[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = v[q];
+        if (rot & 1) {
+            const float t0 = r[0];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) r[q] = r[q + 1];
+            r[7] = t0;
+        }
+        if (rot & 2) {
+            const float t0 = r[0], t1 = r[1];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) r[q] = r[q + 2];
+            r[6] = t0;
+            r[7] = t1;
+        }
+        if (rot & 4) {
+            const float t0 = r[0], t1 = r[1], t2 = r[2], t3 = r[3];
+            r[0] = r[4]; r[1] = r[5]; r[2] = r[6]; r[3] = r[7];
+            r[4] = t0; r[5] = t1; r[6] = t2; r[7] = t3;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int cq = (q + rot) & 7;
+            const int64_t off = ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) + ((cq & 4) ? dzo : 0);
+            unsafeAtomicAdd(base + off, r[q]);
+        }
     }
 };
 
