@@ -80,6 +80,25 @@ __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, in
           });
 }
 
+// The sample stream of one ray through the bricked volume: feed.run(body) delivers
+// alive = body(k, value, active) for k = 0 .. N-1 (raw samples or their box means).
+template <bool BOX, class Smp>
+struct GatherFeed {
+    const Smp& smp;
+    const RaySeg& r;
+    int arm;
+    float* ring;
+    template <class Fn>
+    __device__ __forceinline__ void run(Fn&& body) const {
+        for_each_value<BOX>(smp, r, arm, ring, body);
+    }
+};
+
+template <int MODE, class Feed>
+__device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lut,
+                                         const RaySeg& r, const Filt& F, Feed& feed,
+                                         float4& res, int& count);
+
 template <int MODE, int RATIO, int DT, int C, bool WIDE, bool BOX>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
@@ -91,7 +110,12 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     res = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     count = N;
 
-    if (RATIO != 0) {
+    if (RATIO == 0) {
+        GatherFeed<BOX, Smp> feed{smp, r, a.p.box_arm, ring};
+        march_tf<MODE>(a, s_lut, r, F, feed, res, count);
+        return;
+    }
+    {
         // Line ratio over two co-registered cubes (Section 4.5): method 1 keeps each cube's
         // maximum with strict '>' and maps max2/max1; method 2 maps the per-sample ratio
         // (DATAMIN -> 0 where cube 1 <= 0) and keeps its maximum with '>='.
@@ -125,14 +149,23 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
                 if (a.p.mip_alpha == 1) res.w = 1.0f;
             }
         }
-        return;
     }
+}
 
+// Transfer functions of Sections 3.1-3.3 over the sample stream of one ray (any feed).
+template <int MODE, class Feed>
+__device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lut,
+                                         const RaySeg& r, const Filt& F, Feed& feed,
+                                         float4& res, int& count) {
+    const int N = r.n;
+    const float n_lut = (float)(a.lut_n - 1);
+    res = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    count = N;
     if (MODE <= SVR_MIPRGB) {
         // Eq. MIP, '>=' so a later sample wins a tie; MIP1/MIP_RGB keep the arg-max index.
         float smax = -INFINITY;
         int kmax = 0;
-        for_each_value<BOX>(smp, r, a.p.box_arm, ring, [&](int k, float v, bool active) -> bool {
+        feed.run([&](int k, float v, bool active) -> bool {
             const float s = F(v);
             if (MODE == SVR_MIP0) {
                 smax = active ? fmaxf(s, smax) : smax;  // MIP0 keeps only the value
@@ -176,7 +209,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     const float inx = 1.0f / (float)a.v.nx, iny = 1.0f / (float)a.v.ny, inz = 1.0f / (float)a.v.nz;
     Rgba t = {0.0f, 0.0f, 0.0f, 0.0f};
     int cnt = 0;
-    for_each_value<BOX>(smp, r, a.p.box_arm, ring, [&](int k, float v, bool active) -> bool {
+    feed.run([&](int k, float v, bool active) -> bool {
         const float s = F(v);
         const float kf = (float)k;
         float cr, cg, cb, op;
@@ -204,12 +237,8 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     if (N > 0) res = make_float4(t.r, t.g, t.b, t.a);
 }
 
-// One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
-// is uniform); lanes outside the image pass inside = false and march no samples.
-template <int MODE, int RATIO, int DT, int C, bool WIDE>
-__device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
-                                           int px, int py, bool inside, float4& res,
-                                           int& count) {
+// filter() of Alg. 1 and the colour-map domain for the launch's parameters.
+__device__ __forceinline__ Filt make_filter(const RenderArgs& a) {
     Filt F;
     F.lo = a.p.clim_lo;
     float hi = a.p.clim_hi;
@@ -229,6 +258,11 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_
         F.base = F.lo;
         F.scale = F.inv;
     }
+    return F;
+}
+
+// The ray of pixel (px, py), or an empty one for lanes outside the image.
+__device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py, bool inside) {
     RaySeg r;
     if (inside) {
         r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
@@ -239,6 +273,17 @@ __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_
         r.p0[0] = r.p0[1] = r.p0[2] = 0.0f;
         r.step[0] = r.step[1] = r.step[2] = 0.0f;
     }
+    return r;
+}
+
+// One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
+// is uniform); lanes outside the image pass inside = false and march no samples.
+template <int MODE, int RATIO, int DT, int C, bool WIDE>
+__device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
+                                           int px, int py, bool inside, float4& res,
+                                           int& count) {
+    const Filt F = make_filter(a);
+    const RaySeg r = pixel_ray(a, px, py, inside);
     if (RATIO == 0 && a.p.box_arm > 0)
         march<MODE, RATIO, DT, C, WIDE, true>(a, s_lut, ring, r, F, res, count);
     else
