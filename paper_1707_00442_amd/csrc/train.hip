@@ -109,14 +109,9 @@ struct VoxAccum {
     // Corner q of the cell is (dx, dy, dz) = (q & 1, (q >> 1) & 1, q >> 2).  Neighbouring
     // rays share corners, so lane l issues corner (q + l) mod 8 at step q: the lanes of one
     // atomic instruction then mostly target distinct addresses (atomics to one address
-    // within an instruction are serialised).
-    __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
-        if (key < 0) return;
-        const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
-        const int64_t dxo = (int64_t)i1 - i0;
-        const int64_t dyo = ((int64_t)j1 - j0) * nx;
-        const int64_t dzo = ((int64_t)l1 - l0) * nx * ny;
-        float* base = G + key;
+    // within an instruction are serialised).  add(q, value) receives corner q.
+    template <class Add>
+    __device__ __forceinline__ void each_corner(Add&& add) const {
         const int rot = (int)(threadIdx.x & 7);
         // rotate (v[0..7]) left by rot with three conditional stages
         float r[8];
@@ -141,32 +136,94 @@ struct VoxAccum {
             r[4] = t0; r[5] = t1; r[6] = t2; r[7] = t3;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int cq = (q + rot) & 7;
-            const int64_t off = ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) + ((cq & 4) ? dzo : 0);
-            unsafeAtomicAdd(base + off, r[q]);
+        for (int q = 0; q < 8; ++q) add((q + rot) & 7, r[q]);
+    }
+    // add the pending corners to the global gradient (nx * ny * nz, x fastest)
+    __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
+        if (key < 0) return;
+        const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
+        const int64_t dxo = (int64_t)i1 - i0;
+        const int64_t dyo = ((int64_t)j1 - j0) * nx;
+        const int64_t dzo = ((int64_t)l1 - l0) * nx * ny;
+        float* base = G + key;
+        each_corner([&](int cq, float x) {
+            unsafeAtomicAdd(base + ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) +
+                            ((cq & 4) ? dzo : 0), x);
+        });
+        key = -1;
+    }
+    // add the pending corners to the workgroup's box of voxels [b0, b0 + bn) (x fastest);
+    // a cell outside the box goes to the global gradient instead
+    __device__ __forceinline__ void flush_box(float* box, const int (&b0)[3], const int (&bn)[3],
+                                              float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
+        if (key < 0) return;
+        const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
+        const int x0 = (int)i0 - b0[0], y0 = (int)j0 - b0[1], z0 = (int)l0 - b0[2];
+        const int x1 = (int)i1 - b0[0], y1 = (int)j1 - b0[1], z1 = (int)l1 - b0[2];
+        if (x0 < 0 || y0 < 0 || z0 < 0 || x1 >= bn[0] || y1 >= bn[1] || z1 >= bn[2]) {
+            flush(G, nx, ny, nz);
+            return;
         }
+        const int dxo = x1 - x0, dyo = (y1 - y0) * bn[0], dzo = (z1 - z0) * bn[0] * bn[1];
+        float* base = box + (z0 * bn[1] + y0) * bn[0] + x0;
+        each_corner([&](int cq, float x) {
+            atomicAdd(base + ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) + ((cq & 4) ? dzo : 0), x);
+        });
+        key = -1;
     }
 };
 
 constexpr int kSub = 4;  // samples per sub-segment (held in registers)
 static_assert(kCkptEvery % kSub == 0, "checkpoint segments split into sub-segments");
+constexpr int kBox = 8192;  // voxels of the workgroup's LDS gradient box (32 KB, <= 2^13)
+constexpr int kWaves = kBlock / 64;
 
-// Backward: the workgroup layout and ray ids of the forward pass.  Each ray walks its
-// checkpoint segments from the last to the first.  A segment is replayed once from its
-// stored state to find the states at its sub-segment starts; each sub-segment, last first,
-// is replayed again into registers (state before each sample and its s) and then run
-// through the reverse recurrence of the normalised compositing step.  Gradients of the
-// table entries go to the workgroup's LDS copy (one global atomic per entry at the end),
-// gradients of the voxels to the eight trilinear corners with hardware float atomics.
+// Minimum (first three) and maximum (last three) of six per-lane integers over the
+// workgroup; every thread receives the result.  The caller separates two calls by a barrier.
+__device__ __forceinline__ void wg_box(int (&b)[6], int (*s_red)[kWaves]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        for (int o = 32; o > 0; o >>= 1) {
+            const int y = __shfl_xor(b[i], o);
+            b[i] = i < 3 ? min(b[i], y) : max(b[i], y);
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s_red[i][threadIdx.x >> 6] = b[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        int m = s_red[i][0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) m = i < 3 ? min(m, s_red[i][w]) : max(m, s_red[i][w]);
+        b[i] = __builtin_amdgcn_readfirstlane(m);  // uniform: keep it in scalar registers
+    }
+}
+
+// Backward: the workgroup layout and ray ids of the forward pass.  The workgroup walks
+// checkpoint segments from the last to the first, segment index by segment index (each
+// ray's segments start at its own first sample).  Within a segment a ray is replayed once
+// from its stored state to find the states at its sub-segment starts; each sub-segment,
+// last first, is replayed again into registers (state before each sample and its s) and
+// then run through the reverse recurrence of the normalised compositing step.  Gradients
+// of the table entries go to the workgroup's LDS copy (one global atomic per entry at the
+// end).  Gradients of the voxels go to the eight trilinear corners: into an LDS box that
+// holds every cell the workgroup's rays visit in the segment when it fits (one global
+// atomic per touched voxel per segment), else straight to global memory with hardware
+// float atomics.
 template <int DT, int C>
 __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
     __shared__ float4 s_tf[kTrainMaxTf + 1];
     __shared__ float s_gtf[kTrainMaxTf * 4];
     __shared__ float4 s_sub[kCkptEvery / kSub][kBlock];  // sub-segment start states
+    __shared__ float s_box[kBox];
+    __shared__ int s_red[6][kWaves];
     const int n = a.tf_n;
+    const bool want_vox = a.grad_vox != nullptr;
     stage_table(s_tf, a.tf, n);
     for (int i = threadIdx.x; i < 4 * n; i += kBlock) s_gtf[i] = 0.0f;
+    if (want_vox)
+        for (int i = threadIdx.x; i < kBox; i += kBlock) s_box[i] = 0.0f;
     __syncthreads();
 
     const int t = xcd_tile((int)blockIdx.x, a.nblocks);
@@ -177,116 +234,160 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
     const int64_t rid = (int64_t)t * kBlock + threadIdx.x;
     const bool inside = px < a.cam.width && py < a.cam.height;
     const int K = inside ? a.kcount[rid] : 0;
-    if (K > 0) {
-        float lo = a.p.clim_lo, hi = a.p.clim_hi;
-        if (!(hi > lo)) {
-            lo = a.v.clim[0];
-            hi = a.v.clim[1];
+    float lo = a.p.clim_lo, hi = a.p.clim_hi;
+    if (!(hi > lo)) {
+        lo = a.v.clim[0];
+        hi = a.v.clim[1];
+    }
+    const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
+    const RaySeg r = ray_segment(a.cam, inside ? px : 0, inside ? py : 0, a.v.nx, a.v.ny,
+                                 a.v.nz, a.p.dt);
+    const Sampler<DT, C, true> smp(a.v);
+    const float kw = a.p.k, minv = a.p.min_val;
+    const float nm1 = (float)(n - 1);
+    const float4 g = K > 0 ? a.grad[(size_t)py * a.cam.width + px] : make_float4(0, 0, 0, 0);
+    float gr = g.x, gg = g.y, gb = g.z, ga = g.w;
+    const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
+    const double xm = a.v.nx - 1, ym = a.v.ny - 1, zm = a.v.nz - 1;
+    TfAccum tfa;
+    VoxAccum vxa;
+    bool in_box = false;  // this segment's voxel gradients go to the LDS box
+    int b0[3] = {0, 0, 0}, bn[3] = {0, 0, 0};
+    // the clamped position of sample k (the forward pass's fetch)
+    auto pos = [&](int k, double (&p)[3]) {
+        const double kd = (double)k;
+        p[0] = fmin(fmax(fma(kd, r.dq[0], r.q0[0]), 0.0), xm);
+        p[1] = fmin(fmax(fma(kd, r.dq[1], r.q0[1]), 0.0), ym);
+        p[2] = fmin(fmax(fma(kd, r.dq[2], r.q0[2]), 0.0), zm);
+    };
+    // normalised value of sample k (filter none)
+    auto sample_s = [&](int k) -> float {
+        const double kd = (double)k;
+        const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
+                            fma(kd, r.dq[2], r.q0[2]));
+        return __saturatef((v - lo) * inv);
+    };
+    auto vox_flush = [&]() {
+        if (in_box)
+            vxa.flush_box(s_box, b0, bn, a.grad_vox, nx, ny, nz);
+        else
+            vxa.flush(a.grad_vox, nx, ny, nz);
+    };
+    // reverse step for sample k with state-before S0 and value s
+    auto reverse = [&](int k, const float4 S0, float s) {
+        const float4 c = table(s_tf, nm1, s);
+        const float a_ = kw * c.w;
+        const float a1 = S0.w;
+        const float a2 = a_ * (1.0f - a1);
+        const float sum = __fadd_rn(a1, a2);  // rounded as in composite()
+        const bool act = sum >= minv;
+        const float al = fmaxf(sum, minv);
+        const float ri = rcp(al);
+        const float w1 = a1 * ri, w2 = a2 * ri, wd = (al - a1) * ri;
+        const float C1r = fmaf(c.x, w2, fmaf(-S0.x, wd, S0.x));  // as composite()
+        const float C1g = fmaf(c.y, w2, fmaf(-S0.y, wd, S0.y));
+        const float C1b = fmaf(c.z, w2, fmaf(-S0.z, wd, S0.z));
+        const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
+        const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (act ? g_al : 0.0f);
+        const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri + (act ? g_al : 0.0f) -
+                           g_a2 * a_;
+        const float gcr = gr * w2, gcg = gg * w2, gcb = gb * w2;
+        const float gop = kw * g_a2 * (1.0f - a1);
+        // table: interval j and weight f of the forward lookup (the entry weights)
+        const float x = s * nm1;
+        int j = (int)x;
+        j = j > n - 2 ? n - 2 : j;
+        const float f = x - (float)j;
+        const float e[8] = {(1.0f - f) * gcr, (1.0f - f) * gcg, (1.0f - f) * gcb,
+                            (1.0f - f) * gop, f * gcr, f * gcg, f * gcb, f * gop};
+        tfa.add(s_gtf, j, e);
+        if (want_vox && s > 0.0f && s < 1.0f) {
+            const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
+            const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
+                              gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
+            const float gv = gs * inv;
+            // the cell and fractions of the forward fetch (double positions)
+            double q[3];
+            pos(k, q);
+            const float fx = (float)__builtin_amdgcn_fract(q[0]);
+            const float fy = (float)__builtin_amdgcn_fract(q[1]);
+            const float fz = (float)__builtin_amdgcn_fract(q[2]);
+            const uint32_t i0 = (uint32_t)q[0], j0 = (uint32_t)q[1], l0 = (uint32_t)q[2];
+            const int64_t key = ((int64_t)l0 * ny + j0) * nx + i0;
+            const float gx0 = gv * (1.0f - fx), gx1 = gv * fx;
+            const float wy0z0 = (1.0f - fy) * (1.0f - fz), wy1z0 = fy * (1.0f - fz);
+            const float wy0z1 = (1.0f - fy) * fz, wy1z1 = fy * fz;
+            const float d8[8] = {gx0 * wy0z0, gx1 * wy0z0, gx0 * wy1z0, gx1 * wy1z0,
+                                 gx0 * wy0z1, gx1 * wy0z1, gx0 * wy1z1, gx1 * wy1z1};
+            if (key != vxa.key) {
+                vox_flush();
+                vxa.key = key;
+                vxa.i0 = i0;
+                vxa.j0 = j0;
+                vxa.l0 = l0;
+#pragma unroll
+                for (int q8 = 0; q8 < 8; ++q8) vxa.v[q8] = d8[q8];
+            } else {
+#pragma unroll
+                for (int q8 = 0; q8 < 8; ++q8) vxa.v[q8] += d8[q8];
+            }
         }
-        const float inv = hi > lo ? 1.0f / (hi - lo) : 0.0f;
-        const RaySeg r = ray_segment(a.cam, px, py, a.v.nx, a.v.ny, a.v.nz, a.p.dt);
-        const Sampler<DT, C, true> smp(a.v);
-        const float kw = a.p.k, minv = a.p.min_val;
-        const float nm1 = (float)(n - 1);
-        const float4 g = a.grad[(size_t)py * a.cam.width + px];
-        float gr = g.x, gg = g.y, gb = g.z, ga = g.w;
-        const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
-        const double xm = a.v.nx - 1, ym = a.v.ny - 1, zm = a.v.nz - 1;
-        TfAccum tfa;
-        VoxAccum vxa;
-        // normalised value of sample k (the forward pass's fetch, filter none)
-        auto sample_s = [&](int k) -> float {
-            const double kd = (double)k;
-            const float v = smp(fma(kd, r.dq[0], r.q0[0]), fma(kd, r.dq[1], r.q0[1]),
-                                fma(kd, r.dq[2], r.q0[2]));
-            return __saturatef((v - lo) * inv);
-        };
-        // reverse step for sample k with state-before S0 and value s
-        auto reverse = [&](int k, const float4 S0, float s) {
-            const float4 c = table(s_tf, nm1, s);
-            const float a_ = kw * c.w;
-            const float a1 = S0.w;
-            const float a2 = a_ * (1.0f - a1);
-            const float sum = __fadd_rn(a1, a2);  // rounded as in composite()
-            const bool act = sum >= minv;
-            const float al = fmaxf(sum, minv);
-            const float ri = rcp(al);
-            const float w1 = a1 * ri, w2 = a2 * ri, wd = (al - a1) * ri;
-            const float C1r = fmaf(c.x, w2, fmaf(-S0.x, wd, S0.x));  // as composite()
-            const float C1g = fmaf(c.y, w2, fmaf(-S0.y, wd, S0.y));
-            const float C1b = fmaf(c.z, w2, fmaf(-S0.z, wd, S0.z));
-            const float g_al = ga - (gr * C1r + gg * C1g + gb * C1b) * ri;
-            const float g_a2 = (gr * c.x + gg * c.y + gb * c.z) * ri + (act ? g_al : 0.0f);
-            const float g_a1 = (gr * S0.x + gg * S0.y + gb * S0.z) * ri + (act ? g_al : 0.0f) -
-                               g_a2 * a_;
-            const float gcr = gr * w2, gcg = gg * w2, gcb = gb * w2;
-            const float gop = kw * g_a2 * (1.0f - a1);
-            // table: interval j and weight f of the forward lookup (the entry weights)
-            const float x = s * nm1;
-            int j = (int)x;
-            j = j > n - 2 ? n - 2 : j;
-            const float f = x - (float)j;
-            const float e[8] = {(1.0f - f) * gcr, (1.0f - f) * gcg, (1.0f - f) * gcb,
-                                (1.0f - f) * gop, f * gcr, f * gcg, f * gcb, f * gop};
-            tfa.add(s_gtf, j, e);
-            if (a.grad_vox != nullptr && s > 0.0f && s < 1.0f) {
-                const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
-                const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
-                                  gcb * (P1.z - P0.z) + gop * (P1.w - P0.w)) * nm1;
-                const float gv = gs * inv;
-                // the cell and fractions of the forward fetch (double positions)
-                const double kd = (double)k;
-                const double px_ = fmin(fmax(fma(kd, r.dq[0], r.q0[0]), 0.0), xm);
-                const double py_ = fmin(fmax(fma(kd, r.dq[1], r.q0[1]), 0.0), ym);
-                const double pz_ = fmin(fmax(fma(kd, r.dq[2], r.q0[2]), 0.0), zm);
-                const float fx = (float)__builtin_amdgcn_fract(px_);
-                const float fy = (float)__builtin_amdgcn_fract(py_);
-                const float fz = (float)__builtin_amdgcn_fract(pz_);
-                const uint32_t i0 = (uint32_t)px_, j0 = (uint32_t)py_, l0 = (uint32_t)pz_;
-                const int64_t key = ((int64_t)l0 * ny + j0) * nx + i0;
-                const float gx0 = gv * (1.0f - fx), gx1 = gv * fx;
-                const float wy0z0 = (1.0f - fy) * (1.0f - fz), wy1z0 = fy * (1.0f - fz);
-                const float wy0z1 = (1.0f - fy) * fz, wy1z1 = fy * fz;
-                const float d8[8] = {gx0 * wy0z0, gx1 * wy0z0, gx0 * wy1z0, gx1 * wy1z0,
-                                     gx0 * wy0z1, gx1 * wy0z1, gx0 * wy1z1, gx1 * wy1z1};
-                if (key != vxa.key) {
-                    vxa.flush(a.grad_vox, nx, ny, nz);
-                    vxa.key = key;
-                    vxa.i0 = i0;
-                    vxa.j0 = j0;
-                    vxa.l0 = l0;
+        gr *= w1;
+        gg *= w1;
+        gb *= w1;
+        ga = g_a1;
+    };
+    // one sub-segment, last sample first: replay into registers, then reverse
+    auto sub_segment = [&](int kb, int k1, Rgba st) {
+        float4 S[kSub];
+        float sv[kSub];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) vxa.v[q] = d8[q];
-                } else {
+        for (int i = 0; i < kSub; ++i) {
+            S[i] = make_float4(st.r, st.g, st.b, st.a);
+            sv[i] = 0.0f;
+            if (kb + i < k1) {
+                sv[i] = sample_s(kb + i);
+                avip_step(st, table(s_tf, nm1, sv[i]), kw, minv);
+            }
+        }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) vxa.v[q] += d8[q];
+        for (int i = kSub - 1; i >= 0; --i)
+            if (kb + i < k1) reverse(kb + i, S[i], sv[i]);
+    };
+    // segment count of the workgroup (lanes without samples have none)
+    const int myseg = K > 0 ? (K - 1) / kCkptEvery : -1;
+    int nb[6] = {0, 0, 0, myseg, 0, 0};
+    wg_box(nb, s_red);
+    for (int seg = nb[3]; seg >= 0; --seg) {
+        const bool mine = seg <= myseg;
+        const int k0 = seg * kCkptEvery;
+        const int k1 = mine ? min(k0 + kCkptEvery, K) : k0;
+        if (want_vox) {
+            // cells of this segment: positions are monotone in k, so the first and the
+            // last sample bound them; corners reach one further, up to n - 1
+            int bb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+            if (mine) {
+                double pa[3], pb[3];
+                pos(k0, pa);
+                pos(k1 - 1, pb);
+                const int nmax[3] = {(int)nx - 1, (int)ny - 1, (int)nz - 1};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    bb[d] = (int)fmin(pa[d], pb[d]);
+                    bb[3 + d] = min((int)fmax(pa[d], pb[d]) + 1, nmax[d]);
                 }
             }
-            gr *= w1;
-            gg *= w1;
-            gb *= w1;
-            ga = g_a1;
-        };
-        // one sub-segment, last sample first: replay into registers, then reverse
-        auto sub_segment = [&](int kb, int k1, Rgba st) {
-            float4 S[kSub];
-            float sv[kSub];
+            __syncthreads();  // s_red of the previous reduction has been read
+            wg_box(bb, s_red);
 #pragma unroll
-            for (int i = 0; i < kSub; ++i) {
-                S[i] = make_float4(st.r, st.g, st.b, st.a);
-                sv[i] = 0.0f;
-                if (kb + i < k1) {
-                    sv[i] = sample_s(kb + i);
-                    avip_step(st, table(s_tf, nm1, sv[i]), kw, minv);
-                }
+            for (int d = 0; d < 3; ++d) {
+                b0[d] = bb[d];
+                bn[d] = bb[3 + d] - bb[d] + 1;
             }
-#pragma unroll
-            for (int i = kSub - 1; i >= 0; --i)
-                if (kb + i < k1) reverse(kb + i, S[i], sv[i]);
-        };
-        for (int seg = (K - 1) / kCkptEvery; seg >= 0; --seg) {
-            const int k0 = seg * kCkptEvery;
-            const int k1 = min(k0 + kCkptEvery, K);
+            in_box = bb[3] >= 0 &&
+                     (int64_t)bn[0] * bn[1] * bn[2] <= (int64_t)kBox;
+        }
+        if (mine) {
             const float4 c0 = a.ckpt[(int64_t)seg * a.nrays + rid];
             // states at the sub-segment starts (LDS, one slot per lane)
             Rgba st{c0.x, c0.y, c0.z, c0.w};
@@ -301,10 +402,31 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
                 const float4 q = s_sub[u][threadIdx.x];
                 sub_segment(k0 + u * kSub, k1, Rgba{q.x, q.y, q.z, q.w});
             }
+            if (want_vox) vox_flush();
         }
-        tfa.flush(s_gtf);
-        if (a.grad_vox != nullptr) vxa.flush(a.grad_vox, nx, ny, nz);
+        if (in_box) {
+            // the box to global memory, one atomic per touched voxel; the box is left zero.
+            // Element e = (ez * bn1 + ey) * bn0 + ex; the quotients use reciprocal
+            // multipliers m = floor((2^32 - 1) / d) + 1, exact for e, d <= 2^13 (kBox).
+            __syncthreads();
+            const uint32_t nxy = (uint32_t)(bn[0] * bn[1]), vol = nxy * (uint32_t)bn[2];
+            const uint32_t m0 = 0xffffffffu / (uint32_t)bn[0] + 1u, m1 = 0xffffffffu / nxy + 1u;
+            float* G0 = a.grad_vox + ((int64_t)b0[2] * ny + b0[1]) * nx + b0[0];
+            const int64_t sxy = (int64_t)nx * ny;
+            for (uint32_t e = threadIdx.x; e < vol; e += kBlock) {
+                const float v = s_box[e];
+                if (v != 0.0f) {
+                    const uint32_t ez = nxy > 1 ? __umulhi(e, m1) : e;
+                    const uint32_t rem = e - ez * nxy;
+                    const uint32_t ey = bn[0] > 1 ? __umulhi(rem, m0) : rem;
+                    const uint32_t ex = rem - ey * (uint32_t)bn[0];
+                    unsafeAtomicAdd(G0 + (int64_t)ez * sxy + (int64_t)ey * nx + ex, v);
+                    s_box[e] = 0.0f;
+                }
+            }
+        }
     }
+    tfa.flush(s_gtf);
     __syncthreads();
     for (int i = threadIdx.x; i < 4 * n; i += kBlock) {
         const float v = s_gtf[i];

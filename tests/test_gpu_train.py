@@ -135,6 +135,22 @@ def test_gradients_full_size_sampled_rays(svr):
     assert e_tf <= GTOL and e_vox <= GTOL
 
 
+def test_gradients_coarse_pixels(svr):
+    """Pixels several voxels wide: a 16x16 tile's rays spread over more voxels per segment
+    than the workgroup's LDS gradient box holds, so voxel gradients take the direct
+    global-atomic route."""
+    cube = synth.disc_cube(96, 80, 120, 3, seed=11, dv_chan=8.0, centre_margin=12.0,
+                           rd_range=(4.0, 9.0), zsys_margin=20.0)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.perspective_lookat(96, 80, 120, 40.0, 25.0, 200.0, 40.0, 24, 20).as_f32()
+    tf = (0.02 + 0.5 * synth.tf_bumps(64, seed=4)).astype(np.float32)
+    got, ref, gtf, otf, gvox, ovox, frag = _grad_case(svr, cube, cam, tf, lo, hi, 0.1, 4)
+    e_tf, e_vox = _rel(gtf, otf), _rel(gvox, ovox)
+    print(f"[coarse] tf {e_tf:.2e} vox {e_vox:.2e} fragile {frag.sum()}", flush=True)
+    assert float(np.abs(got - ref).max()) <= 1e-5
+    assert e_tf <= GTOL and e_vox <= GTOL
+
+
 def test_renderfn_autograd(svr):
     """torch.autograd through RenderFn: loss = sum((I - T)^2) against a target rendered
     with hidden control points; gradients match the oracle's."""
