@@ -102,17 +102,52 @@ struct TfAccum {
     }
 };
 
+// Table-gradient window of one lane: entries [base, base + 8) held in registers.  A ray's
+// samples mostly stay within a few neighbouring table intervals (the noise floor of the
+// cube), so the window takes most updates with plain adds; an interval outside it goes to
+// the flush-on-change accumulator.  The window is placed around the first interval seen.
+struct TfWindow {
+    int base = -1;
+    float w[8][4] = {};
+    // entries j and j + 1 get weights 1 - f and f of gc; false if they are not both inside
+    __device__ __forceinline__ bool add(int j, float f, const float (&gc)[4], int n) {
+        if (base < 0) base = max(0, min(j - 3, n - 8));
+        const int rel = j - base;
+        if (rel < 0 || rel > 6) return false;
+        const float wj = 1.0f - f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float wq = q == rel ? wj : (q == rel + 1 ? f : 0.0f);
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) w[q][ch] = fmaf(wq, gc[ch], w[q][ch]);
+        }
+        return true;
+    }
+    __device__ __forceinline__ void flush(float* s_gtf, int n) const {
+        if (base < 0) return;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                if (base + q < n && w[q][ch] != 0.0f) atomicAdd(&s_gtf[4 * (base + q) + ch], w[q][ch]);
+    }
+};
+
 struct VoxAccum {
     int64_t key = -1;  // linear index of the cell's first corner
     uint32_t i0 = 0, j0 = 0, l0 = 0;
     float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // Corner q of the cell is (dx, dy, dz) = (q & 1, (q >> 1) & 1, q >> 2).  Neighbouring
-    // rays share corners, so lane l issues corner (q + l) mod 8 at step q: the lanes of one
-    // atomic instruction then mostly target distinct addresses (atomics to one address
-    // within an instruction are serialised).  add(q, value) receives corner q.
+    // rays share corners, so lane l (pixel (l mod 8, l / 8) of the wave's 8 x 8 block)
+    // issues corner (q + rot) mod 8 at step q with rot = (l + 3 (l / 8)) mod 8: the eight
+    // lanes of a pixel row, of a pixel column and of every 2 x 2 block get distinct
+    // rotations, so the lanes of one atomic instruction mostly target distinct addresses
+    // (atomics to one address within an instruction are serialised).  add(q, value)
+    // receives corner q.
     template <class Add>
     __device__ __forceinline__ void each_corner(Add&& add) const {
-        const int rot = (int)(threadIdx.x & 7);
+        const int l = (int)(threadIdx.x & 63);
+        const int rot = (l + 3 * (l >> 3)) & 7;
         // rotate (v[0..7]) left by rot with three conditional stages
         float r[8];
 #pragma unroll
@@ -175,7 +210,11 @@ struct VoxAccum {
 
 constexpr int kSub = 4;  // samples per sub-segment (held in registers)
 static_assert(kCkptEvery % kSub == 0, "checkpoint segments split into sub-segments");
-constexpr int kBox = 8192;  // voxels of the workgroup's LDS gradient box (32 KB, <= 2^13)
+constexpr int kBox = 4096;  // voxels of the workgroup's LDS gradient box (16 KB, <= 2^13)
+// LDS copies of the table gradient: lane t adds into copy t mod ncopy, so lanes whose rays
+// sit in the same table interval mostly hit different copies; copies are 4 n + 1 floats
+// apart, which puts one entry's copies in different LDS banks.
+constexpr int kGtfLds = 4096;
 constexpr int kWaves = kBlock / 64;
 
 // Minimum (first three) and maximum (last three) of six per-lane integers over the
@@ -207,21 +246,25 @@ __device__ __forceinline__ void wg_box(int (&b)[6], int (*s_red)[kWaves]) {
 // last first, is replayed again into registers (state before each sample and its s) and
 // then run through the reverse recurrence of the normalised compositing step.  Gradients
 // of the table entries go to the workgroup's LDS copy (one global atomic per entry at the
-// end).  Gradients of the voxels go to the eight trilinear corners: into an LDS box that
+// end), through a per-lane register window of eight entries where the samples fall inside
+// it.  Gradients of the voxels go to the eight trilinear corners: into an LDS box that
 // holds every cell the workgroup's rays visit in the segment when it fits (one global
 // atomic per touched voxel per segment), else straight to global memory with hardware
 // float atomics.
 template <int DT, int C>
 __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
     __shared__ float4 s_tf[kTrainMaxTf + 1];
-    __shared__ float s_gtf[kTrainMaxTf * 4];
+    __shared__ float s_gtf[kGtfLds];
     __shared__ float4 s_sub[kCkptEvery / kSub][kBlock];  // sub-segment start states
     __shared__ float s_box[kBox];
     __shared__ int s_red[6][kWaves];
     const int n = a.tf_n;
     const bool want_vox = a.grad_vox != nullptr;
     stage_table(s_tf, a.tf, n);
-    for (int i = threadIdx.x; i < 4 * n; i += kBlock) s_gtf[i] = 0.0f;
+    const int gstride = 4 * n + 1;
+    const int ncopy = min(16, kGtfLds / gstride);
+    for (int i = threadIdx.x; i < kGtfLds; i += kBlock) s_gtf[i] = 0.0f;
+    float* const my_gtf = s_gtf + (int)(threadIdx.x % (unsigned)ncopy) * gstride;
     if (want_vox)
         for (int i = threadIdx.x; i < kBox; i += kBlock) s_box[i] = 0.0f;
     __syncthreads();
@@ -250,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
     const uint32_t nx = (uint32_t)a.v.nx, ny = (uint32_t)a.v.ny, nz = (uint32_t)a.v.nz;
     const double xm = a.v.nx - 1, ym = a.v.ny - 1, zm = a.v.nz - 1;
     TfAccum tfa;
+    TfWindow tfw;
     VoxAccum vxa;
     bool in_box = false;  // this segment's voxel gradients go to the LDS box
     int b0[3] = {0, 0, 0}, bn[3] = {0, 0, 0};
@@ -298,9 +342,12 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
         int j = (int)x;
         j = j > n - 2 ? n - 2 : j;
         const float f = x - (float)j;
-        const float e[8] = {(1.0f - f) * gcr, (1.0f - f) * gcg, (1.0f - f) * gcb,
-                            (1.0f - f) * gop, f * gcr, f * gcg, f * gcb, f * gop};
-        tfa.add(s_gtf, j, e);
+        const float gcv[4] = {gcr, gcg, gcb, gop};
+        if (!tfw.add(j, f, gcv, n)) {
+            const float e[8] = {(1.0f - f) * gcr, (1.0f - f) * gcg, (1.0f - f) * gcb,
+                                (1.0f - f) * gop, f * gcr, f * gcg, f * gcb, f * gop};
+            tfa.add(my_gtf, j, e);
+        }
         if (want_vox && s > 0.0f && s < 1.0f) {
             const float4 P0 = s_tf[j], P1 = s_tf[j + 1];
             const float gs = (gcr * (P1.x - P0.x) + gcg * (P1.y - P0.y) +
@@ -426,10 +473,12 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
             }
         }
     }
-    tfa.flush(s_gtf);
+    tfa.flush(my_gtf);
+    tfw.flush(my_gtf, n);
     __syncthreads();
     for (int i = threadIdx.x; i < 4 * n; i += kBlock) {
-        const float v = s_gtf[i];
+        float v = 0.0f;
+        for (int q = 0; q < ncopy; ++q) v += s_gtf[q * gstride + i];
         if (v != 0.0f) unsafeAtomicAdd(a.grad_tf + i, v);
     }
 }
