@@ -143,9 +143,9 @@ struct VoxAccum {
     // lanes of a pixel row, of a pixel column and of every 2 x 2 block get distinct
     // rotations, so the lanes of one atomic instruction mostly target distinct addresses
     // (atomics to one address within an instruction are serialised).  add(q, value)
-    // receives corner q.
+    // receives corner q, for the corners set in mask.
     template <class Add>
-    __device__ __forceinline__ void each_corner(Add&& add) const {
+    __device__ __forceinline__ void each_corner(unsigned mask, Add&& add) const {
         const int l = (int)(threadIdx.x & 63);
         const int rot = (l + 3 * (l >> 3)) & 7;
         // rotate (v[0..7]) left by rot with three conditional stages
@@ -171,37 +171,42 @@ struct VoxAccum {
             r[4] = t0; r[5] = t1; r[6] = t2; r[7] = t3;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) add((q + rot) & 7, r[q]);
+        for (int q = 0; q < 8; ++q) {
+            const int cq = (q + rot) & 7;
+            if ((mask >> cq) & 1u) add(cq, r[q]);
+        }
     }
-    // add the pending corners to the global gradient (nx * ny * nz, x fastest)
-    __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
+    // add the pending corners in mask to the global gradient (nx * ny * nz, x fastest)
+    __device__ __forceinline__ void flush(float* G, uint32_t nx, uint32_t ny, uint32_t nz,
+                                          unsigned mask = 0xffu) {
         if (key < 0) return;
         const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
         const int64_t dxo = (int64_t)i1 - i0;
         const int64_t dyo = ((int64_t)j1 - j0) * nx;
         const int64_t dzo = ((int64_t)l1 - l0) * nx * ny;
         float* base = G + key;
-        each_corner([&](int cq, float x) {
+        each_corner(mask, [&](int cq, float x) {
             unsafeAtomicAdd(base + ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) +
                             ((cq & 4) ? dzo : 0), x);
         });
         key = -1;
     }
-    // add the pending corners to the workgroup's box of voxels [b0, b0 + bn) (x fastest);
-    // a cell outside the box goes to the global gradient instead
+    // add the pending corners in mask to the workgroup's box of voxels [b0, b0 + bn)
+    // (x fastest); a cell outside the box goes to the global gradient instead
     __device__ __forceinline__ void flush_box(float* box, const int (&b0)[3], const int (&bn)[3],
-                                              float* G, uint32_t nx, uint32_t ny, uint32_t nz) {
+                                              float* G, uint32_t nx, uint32_t ny, uint32_t nz,
+                                              unsigned mask = 0xffu) {
         if (key < 0) return;
         const uint32_t i1 = min(i0 + 1, nx - 1), j1 = min(j0 + 1, ny - 1), l1 = min(l0 + 1, nz - 1);
         const int x0 = (int)i0 - b0[0], y0 = (int)j0 - b0[1], z0 = (int)l0 - b0[2];
         const int x1 = (int)i1 - b0[0], y1 = (int)j1 - b0[1], z1 = (int)l1 - b0[2];
         if (x0 < 0 || y0 < 0 || z0 < 0 || x1 >= bn[0] || y1 >= bn[1] || z1 >= bn[2]) {
-            flush(G, nx, ny, nz);
+            flush(G, nx, ny, nz, mask);
             return;
         }
         const int dxo = x1 - x0, dyo = (y1 - y0) * bn[0], dzo = (z1 - z0) * bn[0] * bn[1];
         float* base = box + (z0 * bn[1] + y0) * bn[0] + x0;
-        each_corner([&](int cq, float x) {
+        each_corner(mask, [&](int cq, float x) {
             atomicAdd(base + ((cq & 1) ? dxo : 0) + ((cq & 2) ? dyo : 0) + ((cq & 4) ? dzo : 0), x);
         });
         key = -1;
@@ -311,11 +316,11 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
                             fma(kd, r.dq[2], r.q0[2]));
         return __saturatef((v - lo) * inv);
     };
-    auto vox_flush = [&]() {
+    auto vox_flush = [&](unsigned mask) {
         if (in_box)
-            vxa.flush_box(s_box, b0, bn, a.grad_vox, nx, ny, nz);
+            vxa.flush_box(s_box, b0, bn, a.grad_vox, nx, ny, nz, mask);
         else
-            vxa.flush(a.grad_vox, nx, ny, nz);
+            vxa.flush(a.grad_vox, nx, ny, nz, mask);
     };
     // reverse step for sample k with state-before S0 and value s
     auto reverse = [&](int k, const float4 S0, float s) {
@@ -367,13 +372,38 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
             const float d8[8] = {gx0 * wy0z0, gx1 * wy0z0, gx0 * wy1z0, gx1 * wy1z0,
                                  gx0 * wy0z1, gx1 * wy0z1, gx0 * wy1z1, gx1 * wy1z1};
             if (key != vxa.key) {
-                vox_flush();
+                // A step to a face-adjacent cell keeps the four corners of the shared face
+                // (axis bit b, +-1): only the corners left behind are flushed.  At the
+                // upper volume edge both cells' corners map to the same clamped voxels.
+                unsigned mask = 0xffu;
+                int b = 0;
+                if (vxa.key >= 0) {
+                    const int di = (int)i0 - (int)vxa.i0, dj = (int)j0 - (int)vxa.j0;
+                    const int dl = (int)l0 - (int)vxa.l0;
+                    if (abs(di) + abs(dj) + abs(dl) == 1) {
+                        b = di != 0 ? 1 : (dj != 0 ? 2 : 4);
+                        const unsigned lower = b == 1 ? 0x55u : (b == 2 ? 0x33u : 0x0fu);
+                        mask = di + dj + dl > 0 ? lower : (~lower & 0xffu);
+                    }
+                }
+                vox_flush(mask);
+                float nv[8];
+#pragma unroll
+                for (int q8 = 0; q8 < 8; ++q8) {
+                    // new corner q8 continues old corner q8 ^ b when that one was kept (the
+                    // three candidates are read first: a select between array elements
+                    // would become a dynamic index and move the array to scratch memory)
+                    const float o1 = vxa.v[q8 ^ 1], o2 = vxa.v[q8 ^ 2], o4 = vxa.v[q8 ^ 4];
+                    const float ov = b == 1 ? o1 : (b == 2 ? o2 : o4);
+                    const bool kept = b != 0 && !((mask >> (q8 ^ b)) & 1u);
+                    nv[q8] = kept ? d8[q8] + ov : d8[q8];
+                }
                 vxa.key = key;
                 vxa.i0 = i0;
                 vxa.j0 = j0;
                 vxa.l0 = l0;
 #pragma unroll
-                for (int q8 = 0; q8 < 8; ++q8) vxa.v[q8] = d8[q8];
+                for (int q8 = 0; q8 < 8; ++q8) vxa.v[q8] = nv[q8];
             } else {
 #pragma unroll
                 for (int q8 = 0; q8 < 8; ++q8) vxa.v[q8] += d8[q8];
@@ -449,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
                 const float4 q = s_sub[u][threadIdx.x];
                 sub_segment(k0 + u * kSub, k1, Rgba{q.x, q.y, q.z, q.w});
             }
-            if (want_vox) vox_flush();
+            if (want_vox) vox_flush(0xffu);
         }
         if (in_box) {
             // the box to global memory, one atomic per touched voxel; the box is left zero.
