@@ -176,7 +176,7 @@ svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t 
     d.dtype = storage;
     d.brick = brick;
     const int E = brick + 1;
-    d.pitch = (uint32_t)(((E * E * E) + 63) / 64 * 64);
+    d.pitch = (uint32_t)((brick_elems(storage, brick) + 63) / 64 * 64);
     const uint64_t nbricks = (uint64_t)d.nbx * d.nby * d.nbz;
     const uint64_t elems = nbricks * d.pitch;
     if (elems >= (1ull << 32) || nbricks >= (1ull << 24)) {

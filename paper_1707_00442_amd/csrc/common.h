@@ -15,17 +15,33 @@ constexpr int kCkptEvery = 32;       // samples between stored ray states (adjoi
 
 // Device view of a bricked volume.  Brick (bx, by, bz) holds voxels [C*b, C*b + C] per axis
 // (C + 1 = E stored per axis; the last layer is the apron = first layer of the next brick,
-// or a replica of the cube's last voxel).  Element (lx, ly, lz) of a brick sits at
-// brick_index * pitch + (lz * E + ly) * E + lx, brick_index = (bz * nby + by) * nbx + bx.
+// or a replica of the cube's last voxel); brick_index = (bz * nby + by) * nbx + bx.
+//   float32: voxel (lx, ly, lz) of a brick sits at brick_index * pitch + (lz * E + ly) * E + lx.
+//   16-bit:  y-pairs.  Pair (lx, ly, lz), ly < C, holds voxels (lx, ly, lz) and (lx, ly + 1, lz)
+//            as two consecutive elements at brick_index * pitch + 2 ((lz * C + ly) * E + lx),
+//            so one 8-byte load returns the four corners (x, x + 1) x (y, y + 1) of a cell face.
 struct VolDesc {
     const void* data;
     int32_t nx, ny, nz;
     int32_t nbx, nby, nbz;
     int32_t dtype;
     int32_t brick;        // C
-    uint32_t pitch;       // elements per brick (E^3 rounded up to 64)
+    uint32_t pitch;       // elements per brick (stored elements rounded up to 64)
     const float* clim;    // device: [finite min, finite max] of the stored values
 };
+
+// Stored elements of one brick: E^3 for float32, E C E pairs for 16-bit storage.
+__host__ __device__ constexpr int brick_elems(int dtype, int C) {
+    return dtype == SVR_F32 ? (C + 1) * (C + 1) * (C + 1) : 2 * (C + 1) * C * (C + 1);
+}
+
+// In-brick element offset of voxel (lx, ly, lz), ly < C for 16-bit storage (the first element
+// of its pair; the pair of ly - 1 holds it too).
+template <int DT, int C>
+__host__ __device__ __forceinline__ uint32_t brick_loc(uint32_t lx, uint32_t ly, uint32_t lz) {
+    constexpr uint32_t E = C + 1;
+    return DT == SVR_F32 ? (lz * E + ly) * E + lx : 2u * ((lz * C + ly) * E + lx);
+}
 
 // Element loaders: stored type -> float32.
 template <int DT> struct Elem;

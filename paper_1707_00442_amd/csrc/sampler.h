@@ -11,6 +11,8 @@ namespace svr {
 // local offset, and the eight corners are read at compile-time offsets from one address
 // (the apron holds the +1 neighbours, so no corner leaves the brick and the upper edge
 // needs no index clamp).  Interpolation order x, then y, then z, each a + f (b - a).
+// Float32 storage reads the corners as four (x, x + 1) pairs; 16-bit storage (y-pair
+// layout) as two runs of four elements, the faces z and z + 1 of the cell.
 //
 // WIDE = false addresses the storage with 32-bit byte offsets from a scalar base (volumes
 // below 4 GiB); WIDE = true forms 64-bit addresses.
@@ -47,8 +49,7 @@ struct Sampler {
         __builtin_assume(b <= kM24);
         b = b * nbx + (ix >> SH);
         __builtin_assume(b <= kM24);
-        const uint32_t loc = ((iz & (C - 1)) * E + (iy & (C - 1))) * E + (ix & (C - 1));
-        return b * pitch + loc;
+        return b * pitch + brick_loc<DT, C>(ix & (C - 1), iy & (C - 1), iz & (C - 1));
     }
 
     __device__ __forceinline__ const T* at(uint32_t off) const {
@@ -68,14 +69,26 @@ struct Sampler {
         f.fy = (float)__builtin_amdgcn_fract(y);
         f.fz = (float)__builtin_amdgcn_fract(z);
         const T* q = at(offset((uint32_t)x, (uint32_t)y, (uint32_t)z));
-        f.c000 = Elem<DT>::get(q, 0);
-        f.c100 = Elem<DT>::get(q, 1);
-        f.c010 = Elem<DT>::get(q, E);
-        f.c110 = Elem<DT>::get(q, E + 1);
-        f.c001 = Elem<DT>::get(q, E * E);
-        f.c101 = Elem<DT>::get(q, E * E + 1);
-        f.c011 = Elem<DT>::get(q, E * E + E);
-        f.c111 = Elem<DT>::get(q, E * E + E + 1);
+        if constexpr (DT == SVR_F32) {
+            f.c000 = Elem<DT>::get(q, 0);
+            f.c100 = Elem<DT>::get(q, 1);
+            f.c010 = Elem<DT>::get(q, E);
+            f.c110 = Elem<DT>::get(q, E + 1);
+            f.c001 = Elem<DT>::get(q, E * E);
+            f.c101 = Elem<DT>::get(q, E * E + 1);
+            f.c011 = Elem<DT>::get(q, E * E + E);
+            f.c111 = Elem<DT>::get(q, E * E + E + 1);
+        } else {
+            constexpr uint32_t kZ = 2 * C * E;  // next pair layer
+            f.c000 = Elem<DT>::get(q, 0);
+            f.c010 = Elem<DT>::get(q, 1);
+            f.c100 = Elem<DT>::get(q, 2);
+            f.c110 = Elem<DT>::get(q, 3);
+            f.c001 = Elem<DT>::get(q, kZ);
+            f.c011 = Elem<DT>::get(q, kZ + 1);
+            f.c101 = Elem<DT>::get(q, kZ + 2);
+            f.c111 = Elem<DT>::get(q, kZ + 3);
+        }
         return f;
     }
 

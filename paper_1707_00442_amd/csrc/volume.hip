@@ -265,8 +265,14 @@ __global__ __launch_bounds__(kBlock) void brick_group_kernel(const typename Elem
 #pragma unroll
         for (int m = 0; m < VO; ++m) {
             const int l = (int)q * VO + m;
-            const int lz = l / (E * E), ly = (l / E) % E, lx = l % E;
-            off[m] = l < E * E * E ? (lz * E + ly) * WP + lx : -1;
+            if constexpr (DT_OUT == SVR_F32) {
+                const int lz = l / (E * E), ly = (l / E) % E, lx = l % E;
+                off[m] = l < E * E * E ? (lz * E + ly) * WP + lx : -1;
+            } else {  // y-pairs: element 2 p + h of pair p = (lz C + ly) E + lx is voxel ly + h
+                const int p = l >> 1, h = l & 1;
+                const int lz = p / (C * E), ly = (p / E) % C, lx = p % E;
+                off[m] = p < E * C * E ? (lz * E + ly + h) * WP + lx : -1;
+            }
         }
         for (int k = 0; k < nb; ++k) {
             Vec16<TO> o;
@@ -405,14 +411,13 @@ svr_status launch_upload(const svr_cube_view& c, const VolDesc& d, float* aux, f
 // Bricked storage -> C-contiguous [z][y][x] of the storage type.
 template <int DT, int C>
 __global__ __launch_bounds__(kBlock) void export_kernel(VolDesc v, typename Elem<DT>::T* out) {
-    constexpr int E = C + 1;
     constexpr int SH = C == 8 ? 3 : 4;
     using T = typename Elem<DT>::T;
     const uint32_t x = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
     if (x >= (uint32_t)v.nx) return;
     const uint32_t b = ((z >> SH) * (uint32_t)v.nby + (y >> SH)) * (uint32_t)v.nbx + (x >> SH);
-    const uint32_t loc = ((z & (C - 1)) * E + (y & (C - 1))) * E + (x & (C - 1));
+    const uint32_t loc = brick_loc<DT, C>(x & (C - 1), y & (C - 1), z & (C - 1));
     out[((size_t)z * v.ny + y) * v.nx + x] = ((const T*)v.data)[(size_t)b * v.pitch + loc];
 }
 
