@@ -22,14 +22,19 @@ struct Sampler {
     static constexpr int E = C + 1;
     static constexpr int SH = C == 8 ? 3 : 4;
     static constexpr uint32_t kM24 = 0xffffffu;
+    // Same-cell reuse pays for float32 storage (four 8-byte loads per sample); with two
+    // loads per sample (16-bit storage) its selects and registers cost more than it saves.
+    static constexpr bool kReuse = DT == SVR_F32;
     const T* data;
     double xm, ym, zm;
     uint32_t nbx, nby, pitch;
 
-    // Loads in flight for one sample: its eight corners and the cell fractions.
+    // Loads in flight for one sample: its eight corners and the cell fractions; reuse marks
+    // a sample in the same cell as the one fetched before it (no loads issued, corners 0).
     struct Fetch {
         float c000, c100, c010, c110, c001, c101, c011, c111;
         float fx, fy, fz;
+        bool reuse;
     };
 
     // Brick counts and the pitch are below 2^24 (checked at volume creation); the masks
@@ -61,6 +66,15 @@ struct Sampler {
     // The point (double) is clamped to [0, n-1], so the cell index is its truncation; the
     // fraction point - floor(point) is exact in double (v_fract) and then rounded to float.
     __device__ __forceinline__ Fetch fetch(double x, double y, double z) const {
+        uint32_t none = 0xffffffffu;
+        return fetch_after(x, y, z, none);
+    }
+
+    // As fetch(), but the loads are skipped when the cell is the one at element offset
+    // `last` (the previous sample's); `last` becomes this sample's cell.  Offsets are below
+    // 2^32 - 1, so 0xffffffff matches no cell.
+    __device__ __forceinline__ Fetch fetch_after(double x, double y, double z,
+                                                 uint32_t& last) const {
         x = fmin(fmax(x, 0.0), xm);
         y = fmin(fmax(y, 0.0), ym);
         z = fmin(fmax(z, 0.0), zm);
@@ -68,7 +82,14 @@ struct Sampler {
         f.fx = (float)__builtin_amdgcn_fract(x);
         f.fy = (float)__builtin_amdgcn_fract(y);
         f.fz = (float)__builtin_amdgcn_fract(z);
-        const T* q = at(offset((uint32_t)x, (uint32_t)y, (uint32_t)z));
+        const uint32_t o = offset((uint32_t)x, (uint32_t)y, (uint32_t)z);
+        f.reuse = kReuse && o == last;
+        last = o;
+        if (f.reuse) {
+            f.c000 = f.c100 = f.c010 = f.c110 = f.c001 = f.c101 = f.c011 = f.c111 = 0.0f;
+            return f;
+        }
+        const T* q = at(o);
         if constexpr (DT == SVR_F32) {
             f.c000 = Elem<DT>::get(q, 0);
             f.c100 = Elem<DT>::get(q, 1);
@@ -109,24 +130,44 @@ struct Sampler {
 
 // Samples along one ray, fetched in order: fetch number j (j = 0, 1, 2, ...) is the sample
 // at q0 + (j + base) dq.  The position is advanced in double by one step per fetch; the
-// accumulated rounding stays below 1e-9 voxel for any realistic ray length.
+// accumulated rounding stays below 1e-9 voxel for any realistic ray length.  At steps below
+// a voxel consecutive samples often share a cell: such a sample issues no loads and value()
+// blends it from the corners of the last sample that loaded (values are taken in fetch
+// order, so those are the previous sample's corners).
 template <class S>
 struct RaySource {
     using Fetch = typename S::Fetch;
     const S& smp;
     double px, py, pz, dqx, dqy, dqz;
+    uint32_t last = 0xffffffffu;
+    Fetch lc{};  // corners of the last blended sample that loaded
     __device__ __forceinline__ RaySource(const S& s, const RaySeg& r, float base)
         : smp(s), px(fma((double)base, r.dq[0], r.q0[0])),
           py(fma((double)base, r.dq[1], r.q0[1])), pz(fma((double)base, r.dq[2], r.q0[2])),
           dqx(r.dq[0]), dqy(r.dq[1]), dqz(r.dq[2]) {}
     __device__ __forceinline__ Fetch next() {
-        const Fetch f = smp.fetch(px, py, pz);
+        const Fetch f = smp.fetch_after(px, py, pz, last);
         px += dqx;
         py += dqy;
         pz += dqz;
         return f;
     }
-    static __device__ __forceinline__ float value(const Fetch& f) { return S::blend(f); }
+    __device__ __forceinline__ float value(const Fetch& f) {
+        if constexpr (!S::kReuse) return S::blend(f);
+        const bool r = f.reuse;
+        lc.c000 = r ? lc.c000 : f.c000;
+        lc.c100 = r ? lc.c100 : f.c100;
+        lc.c010 = r ? lc.c010 : f.c010;
+        lc.c110 = r ? lc.c110 : f.c110;
+        lc.c001 = r ? lc.c001 : f.c001;
+        lc.c101 = r ? lc.c101 : f.c101;
+        lc.c011 = r ? lc.c011 : f.c011;
+        lc.c111 = r ? lc.c111 : f.c111;
+        lc.fx = f.fx;
+        lc.fy = f.fy;
+        lc.fz = f.fz;
+        return S::blend(lc);
+    }
 };
 
 // The same point sampled in two co-registered volumes (line ratios).
@@ -139,8 +180,9 @@ struct PairSource {
     __device__ __forceinline__ PairSource(const S& s1, const S& s2, const RaySeg& r)
         : ra(s1, r, 0.0f), rb(s2, r, 0.0f) {}
     __device__ __forceinline__ Fetch next() { return Fetch{ra.next(), rb.next()}; }
-    static __device__ __forceinline__ float2 value(const Fetch& f) {
-        return make_float2(S::blend(f.a), S::blend(f.b));
+    __device__ __forceinline__ float2 value(const Fetch& f) {
+        const float va = ra.value(f.a);
+        return make_float2(va, rb.value(f.b));
     }
 };
 
@@ -159,11 +201,11 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
     bool alive = true;
     for (int j = 0;; j += 3) {
         typename Src::Fetch q2 = src.next();
-        alive = body(j, Src::value(q0), alive && j < n);
+        alive = body(j, src.value(q0), alive && j < n);
         q0 = src.next();
-        alive = body(j + 1, Src::value(q1), alive && j + 1 < n);
+        alive = body(j + 1, src.value(q1), alive && j + 1 < n);
         q1 = src.next();
-        alive = body(j + 2, Src::value(q2), alive && j + 2 < n);
+        alive = body(j + 2, src.value(q2), alive && j + 2 < n);
         if (!wave_any(alive && j + 3 < n)) break;
     }
 }
