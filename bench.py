@@ -56,12 +56,13 @@ KERNEL_SOURCES = {
     "smooth": ("common.h", "smooth.hip"),
     "line_ratio": ("common.h", "smooth.hip"),
     "upload": ("common.h", "volume.hip"),
+    "train": ("common.h", "sampler.h", "train.hip"),
     "copy": (),
 }
 
 
 def kernel_family(kernel):
-    for fam in ("render", "smooth", "line_ratio", "upload", "copy"):
+    for fam in ("render", "smooth", "line_ratio", "upload", "train", "copy"):
         if kernel.startswith(fam):
             return fam
     raise KeyError(kernel)
@@ -90,7 +91,8 @@ def parse():
     ap.add_argument("--profile", default=None,
                     help="run only this kernel on the main workload, --steps times (for "
                          "rocprofv3): render_<mode>, render_sparse, smooth_sigma<s>, upload, "
-                         "line_ratio, copy (a 1 GiB device copy used to scale the counters)")
+                         "line_ratio, train_fwd, train_bwd, copy (a 1 GiB device copy used to "
+                         "scale the counters)")
     return ap.parse_args()
 
 
@@ -336,6 +338,23 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
         fn = lambda: svr.svr_volume_upload(vol, cube)  # noqa: E731
     elif name == "line_ratio":
         fn = lambda: svr.svr_line_ratio(cube, 400, 600, 32, 3.0, 3.0, lo, out=ratio_out)  # noqa: E731,E501
+    elif name in ("train_fwd", "train_bwd"):
+        # the differentiable form: 256^3 cube, 1024x1024, 64-point transfer function
+        c4 = torch.from_numpy(synth.cfg4_cube(0)).cuda()
+        l4, h4 = svr.svr_minmax(c4)
+        v4 = svr.svr_volume_create(c4)
+        tf = torch.from_numpy(synth.tf_ramp(64)).cuda()
+        p4 = dict(mode="avip0", opacity_from_lut=1, k=0.22, clim_lo=l4, clim_hi=h4)
+        cam4 = synth.perspective_lookat(256, 256, 256, 30.0, 20.0, 256 * 3 ** 0.5, 40.0,
+                                        1024, 1024).as_f32()
+        img, wsp = svr.svr_render_train(v4, cam4, tf, p4)
+        g = torch.randn(1024, 1024, 4, device="cuda")
+        gtf, gvox = torch.zeros_like(tf), torch.zeros_like(c4)
+        if name == "train_fwd":
+            fn = lambda: svr.svr_render_train(v4, cam4, tf, p4, out=img, workspace=wsp)  # noqa: E731,E501
+        else:
+            fn = lambda: svr.svr_render_backward(v4, cam4, tf, p4, wsp, g, grad_tf=gtf,  # noqa: E731
+                                                 grad_vox=gvox)
     else:
         raise SystemExit(f"unknown kernel {name}")
     for i in range(args.steps):

@@ -99,11 +99,11 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
                                          const RaySeg& r, const Filt& F, Feed& feed,
                                          float4& res, int& count);
 
-template <int MODE, int RATIO, int DT, int C, bool WIDE, bool BOX>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, bool BOX, bool REUSE>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
-    using Smp = Sampler<DT, C, WIDE>;
+    using Smp = Sampler<DT, C, WIDE, REUSE>;
     const Smp smp(a.v);
     const int N = r.n;
     const float n_lut = (float)(a.lut_n - 1);
@@ -277,17 +277,18 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 }
 
 // One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
-// is uniform); lanes outside the image pass inside = false and march no samples.
-template <int MODE, int RATIO, int DT, int C, bool WIDE>
+// is uniform); lanes outside the image pass inside = false and march no samples.  REUSE:
+// same-cell corner reuse (float32 storage at steps below a voxel).
+template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
     const Filt F = make_filter(a);
     const RaySeg r = pixel_ray(a, px, py, inside);
     if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, WIDE, true>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, true, REUSE>(a, s_lut, ring, r, F, res, count);
     else
-        march<MODE, RATIO, DT, C, WIDE, false>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, false, REUSE>(a, s_lut, ring, r, F, res, count);
 }
 
 // Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works

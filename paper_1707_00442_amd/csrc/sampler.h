@@ -15,16 +15,18 @@ namespace svr {
 // layout) as two runs of four elements, the faces z and z + 1 of the cell.
 //
 // WIDE = false addresses the storage with 32-bit byte offsets from a scalar base (volumes
-// below 4 GiB); WIDE = true forms 64-bit addresses.
-template <int DT, int C, bool WIDE>
+// below 4 GiB); WIDE = true forms 64-bit addresses.  REUSE enables the same-cell reuse of
+// RaySource (float32 storage only).
+template <int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32>
 struct Sampler {
     using T = typename Elem<DT>::T;
     static constexpr int E = C + 1;
     static constexpr int SH = C == 8 ? 3 : 4;
     static constexpr uint32_t kM24 = 0xffffffu;
-    // Same-cell reuse pays for float32 storage (four 8-byte loads per sample); with two
-    // loads per sample (16-bit storage) its selects and registers cost more than it saves.
-    static constexpr bool kReuse = DT == SVR_F32;
+    // Same-cell reuse pays for float32 storage (four 8-byte loads per sample) at steps below
+    // a voxel; with two loads per sample (16-bit storage), or at steps where every sample
+    // changes cell, its selects and registers cost more than it saves.
+    static constexpr bool kReuse = REUSE && DT == SVR_F32;
     const T* data;
     double xm, ym, zm;
     uint32_t nbx, nby, pitch;
