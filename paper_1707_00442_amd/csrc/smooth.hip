@@ -115,11 +115,7 @@ static svr_status launch_smooth_generic(const svr_cube_view& c, const float* tap
 
 // ---------------------------------------------------------------- fixed tap counts
 // For the common tap counts (the 5-, 9- and 13-tap binomials, the sigma = 1, 2, 3 Gaussians
-// of 7, 13 and 19 taps) the passes are two streaming kernels with compile-time loops:
-//   * x and y fused: a workgroup stages one z-slice tile of the input with its clamped halo
-//     in LDS, filters it along x into a second LDS tile, then along y to float32 output;
-//   * z: every lane produces 16 consecutive outputs of one (y, x) column from 15 + T
-//     inputs read straight from memory (neighbouring lanes read neighbouring x).
+// of 7, 13 and 19 taps) one fused kernel with compile-time loops does all three axes.
 // Each output is the same ordered sum sum_j g[j] v[j] (fma from j = 0 up) as in the generic
 // kernels; only products inside the kernel's support are formed.  Taps are kernel
 // arguments indexed with compile-time offsets, so they sit in scalar registers.
@@ -142,149 +138,179 @@ __device__ __forceinline__ void conv_block(const FixedTaps<T>& g, Fetch&& fetch,
     }
 }
 
-constexpr int kXyTx = 64;  // tile width (x)
-constexpr int kXyTy = 32;  // tile height (y)
-constexpr int kXyR = 8;    // outputs per lane along x (first phase) and along y (second)
+constexpr int kXyR = 8;  // x-phase outputs per lane
 
+// All three axes in one pass.  A workgroup owns a 64 x 16 tile of (x, y) and a run of kFzZ
+// output planes; it walks the input planes z0 - r .. z0 + kFzZ - 1 + r in order.  Each plane's
+// tile and clamped halo is staged in LDS and filtered along x (into a second LDS tile) and
+// along y (into registers); every lane keeps the last T xy-filtered planes of its four
+// outputs in a register ring and, once the ring is full, forms the z sum for the plane r
+// behind.  The next plane's tile is loaded into registers while the current one is filtered.
+// The cube is read about once (the x/y halo is re-read from L2) and written once,
+// with no intermediate cube.  The sums are the ordered sums of the two-kernel form (x, then
+// y, then z, each sum_j g[j] v[j] by fma from j = 0 up), so the result is bit-identical.
+constexpr int kFzTx = 64;  // tile width (x)
+constexpr int kFzTy = 16;  // tile height (y)
+constexpr int kFzRy = 4;   // outputs per lane along y (ring depth kFzRy x T registers)
+constexpr int kFzZ = 128;  // output planes per workgroup
+// Long filters keep the ring as a shift register (T x kFzRy moves per plane); short ones
+// unroll the plane loop T times so the ring rotates with compile-time slots (the unrolled
+// code grows as T^2 and stops fitting the instruction cache).
 template <int T>
-constexpr int xy_lds_floats() {
-    return (kXyTy + T - 1) * (kXyTx + T - 1) + (kXyTy + T - 1) * kXyTx;
-}
+constexpr bool kFzShift = T > 13;
 
-template <int DT_IN, int T>
-__global__ __launch_bounds__(kBlock) void smooth_xy_kernel(const typename Elem<DT_IN>::T* in,
-                                                           float* out, int32_t nx, int32_t ny,
-                                                           int32_t tiles_x, int32_t tiles_y,
-                                                           const FixedTaps<T> g) {
+template <int DT_IN, int DT_OUT, int T>
+__global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
+    const typename Elem<DT_IN>::T* in, typename Elem<DT_OUT>::T* out, int32_t nx, int32_t ny,
+    int32_t nz, int32_t tiles_x, int32_t ntiles, int32_t nblocks, const FixedTaps<T> g) {
     constexpr int r = T / 2;
-    constexpr int AW = kXyTx + T - 1, AH = kXyTy + T - 1;
+    constexpr int AW = kFzTx + T - 1, AH = kFzTy + T - 1;
     __shared__ float A[AH * AW];
-    __shared__ float B[AH * kXyTx];
-    const int64_t t = blockIdx.x;
-    const int tx = (int)(t % tiles_x);
-    const int ty = (int)((t / tiles_x) % tiles_y);
-    const int64_t z = t / ((int64_t)tiles_x * tiles_y);
-    const int x0 = tx * kXyTx, y0 = ty * kXyTy;
-    const typename Elem<DT_IN>::T* slice = in + z * ny * nx;
-    // input tile with clamp-to-edge halo
-    for (int i = threadIdx.x; i < AH * AW; i += kBlock) {
+    __shared__ float B[AH * kFzTx];
+    const int b = xcd_tile((int)blockIdx.x, nblocks);  // neighbouring tiles on one XCD
+    const int tile = b % ntiles, zc = b / ntiles;
+    const int x0 = (tile % tiles_x) * kFzTx, y0 = (tile / tiles_x) * kFzTy;
+    const int z0 = zc * kFzZ;
+    const int64_t plane = (int64_t)nx * ny;
+    const int xl = threadIdx.x & (kFzTx - 1);     // this lane's column
+    const int yg = (threadIdx.x >> 6) * kFzRy;    // and its first row
+    const int gxo = x0 + xl;
+    float ring[T][kFzRy];
+    // planes s = 0 .. nsl - 1 are z = z0 - r + s (clamped to the cube)
+    const int nsl = min(kFzZ, nz - z0) + T - 1;
+    // tile element k of this lane (k < NP): i = threadIdx.x + k * kBlock, row i / AW
+    constexpr int NP = (AH * AW + kBlock - 1) / kBlock;
+    int goff[NP];  // in-plane offset of each staged element (clamped), -1 past the tile
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int i = threadIdx.x + k * kBlock;
         const int ry = i / AW, rx = i - ry * AW;
         int gx = x0 - r + rx, gy = y0 - r + ry;
         gx = gx < 0 ? 0 : (gx > nx - 1 ? nx - 1 : gx);
         gy = gy < 0 ? 0 : (gy > ny - 1 ? ny - 1 : gy);
-        A[i] = Elem<DT_IN>::get(slice, (uint32_t)(gy * nx + gx));
+        goff[k] = i < AH * AW ? gy * nx + gx : -1;
+    }
+    auto plane_ptr = [&](int s) {
+        int zs = z0 - r + s;
+        zs = zs < 0 ? 0 : (zs > nz - 1 ? nz - 1 : zs);
+        return in + (int64_t)zs * plane;
+    };
+    // the next plane's tile, loaded while the current one is filtered (kept in the storage
+    // type: converting at load time would make the loads wait before the filtering)
+    typename Elem<DT_IN>::T pre[NP];
+    {
+        const typename Elem<DT_IN>::T* slice = plane_ptr(0);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            if (goff[k] >= 0) A[threadIdx.x + k * kBlock] = Elem<DT_IN>::get(slice, (uint32_t)goff[k]);
     }
     __syncthreads();
-    // along x: rows 0 .. AH-1, eight lanes per row, kXyR outputs each
-    {
-        const int xg = (threadIdx.x & 7) * kXyR;
-        for (int ry = threadIdx.x >> 3; ry < AH; ry += kBlock / 8) {
-            const float* a = A + ry * AW + xg;
-            float acc[kXyR];
-            conv_block<T, kXyR>(g, [&](int m) { return a[m]; }, acc);
+    // One plane: prefetch the next tile, filter the current one along x and y into ring
+    // slot `slot`, and, once T planes are in, the z sum over slots in age order at(j).
+    auto step = [&](int s, float (&dst)[kFzRy], auto&& at) {
+        const bool more = s + 1 < nsl;
+        if (more) {
+            const typename Elem<DT_IN>::T* slice = plane_ptr(s + 1);
 #pragma unroll
-            for (int q = 0; q < kXyR; ++q) B[ry * kXyTx + xg + q] = acc[q];
+            for (int k = 0; k < NP; ++k)
+                if (goff[k] >= 0) pre[k] = slice[goff[k]];
         }
-    }
-    __syncthreads();
-    // along y: 64 columns x 4 groups of kXyR rows
-    {
-        const int x = threadIdx.x & (kXyTx - 1);
-        const int yg = (threadIdx.x >> 6) * kXyR;
-        const float* b = B + yg * kXyTx + x;
-        float acc[kXyR];
-        conv_block<T, kXyR>(g, [&](int m) { return b[m * kXyTx]; }, acc);
-        const int gx = x0 + x;
-        if (gx < nx) {
+        {
+            const int xg = (threadIdx.x & 7) * kXyR;
+            for (int ry = threadIdx.x >> 3; ry < AH; ry += kBlock / 8) {
+                const float* a = A + ry * AW + xg;
+                float acc[kXyR];
+                conv_block<T, kXyR>(g, [&](int m) { return a[m]; }, acc);
 #pragma unroll
-            for (int q = 0; q < kXyR; ++q) {
-                const int gy = y0 + yg + q;
-                if (gy < ny) out[(z * ny + gy) * nx + gx] = acc[q];
+                for (int q = 0; q < kXyR; ++q) B[ry * kFzTx + xg + q] = acc[q];
             }
+        }
+        __syncthreads();  // B complete; A no longer read
+        {
+            const float* bb = B + yg * kFzTx + xl;
+            conv_block<T, kFzRy>(g, [&](int m) { return bb[m * kFzTx]; }, dst);
+        }
+        if (s >= T - 1) {
+            const int zo = z0 + s - (T - 1);  // output plane
+            float acc[kFzRy];
+#pragma unroll
+            for (int q = 0; q < kFzRy; ++q) acc[q] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                const float* v = at(j);
+#pragma unroll
+                for (int q = 0; q < kFzRy; ++q) acc[q] = fmaf(g.g[j], v[q], acc[q]);
+            }
+            if (gxo < nx) {
+#pragma unroll
+                for (int q = 0; q < kFzRy; ++q) {
+                    const int gy = y0 + yg + q;
+                    if (gy < ny)
+                        out[(int64_t)zo * plane + (int64_t)gy * nx + gxo] = Elem<DT_OUT>::put(acc[q]);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (goff[k] >= 0) A[threadIdx.x + k * kBlock] = Elem<DT_IN>::get(&pre[k], 0);
+        }
+        __syncthreads();  // A holds the next plane; B no longer read
+    };
+    if constexpr (kFzShift<T>) {
+        // shift register: ring[0] is the oldest plane; code size independent of T
+        for (int s = 0; s < nsl; ++s) {
+#pragma unroll
+            for (int j = 0; j + 1 < T; ++j)
+#pragma unroll
+                for (int q = 0; q < kFzRy; ++q) ring[j][q] = ring[j + 1][q];
+            step(s, ring[T - 1], [&](int j) -> const float* { return ring[j]; });
+        }
+    } else {
+        // rotating ring unrolled T times: plane s sits in slot s mod T
+        for (int s0 = 0; s0 < nsl; s0 += T) {
+#pragma unroll
+            for (int u = 0; u < T; ++u)
+                if (s0 + u < nsl)  // uniform over the workgroup
+                    step(s0 + u, ring[u], [&](int j) -> const float* { return ring[(u + 1 + j) % T]; });
         }
     }
 }
 
-constexpr int kZR = 16;  // outputs per lane along z
-
-// Along z (stride plane = nx*ny): lane i of block (column block cb, z block zb) filters column
-// cb*256 + i for outputs zb*kZR .. zb*kZR+kZR-1.  Blocks are numbered with the z block fastest
-// and dealt to XCDs in contiguous runs, so the T-1 halo planes shared by neighbouring z blocks
-// are re-read from the same L2.
-template <int DT_OUT, int T>
-__global__ __launch_bounds__(kBlock) void smooth_z_kernel(const float* in,
-                                                          typename Elem<DT_OUT>::T* out,
-                                                          int64_t plane, int32_t nz,
-                                                          int32_t zblocks, int32_t nblocks,
-                                                          const FixedTaps<T> g) {
-    constexpr int r = T / 2;
-    const int b = xcd_tile((int)blockIdx.x, nblocks);
-    const int zb = b % zblocks;
-    const int64_t i = (int64_t)(b / zblocks) * kBlock + threadIdx.x;
-    if (i >= plane) return;
-    const int z0 = zb * kZR;
-    const float* col = in + i;
-    float acc[kZR];
-    conv_block<T, kZR>(g, [&](int m) {
-        int zz = z0 - r + m;
-        zz = zz < 0 ? 0 : (zz > nz - 1 ? nz - 1 : zz);
-        return col[(int64_t)zz * plane];
-    }, acc);
-#pragma unroll
-    for (int q = 0; q < kZR; ++q)
-        if (z0 + q < nz) out[(int64_t)(z0 + q) * plane + i] = Elem<DT_OUT>::put(acc[q]);
+template <int T, int DT_IN, int DT_OUT>
+static svr_status smooth_fused_launch(const svr_cube_view& c, const FixedTaps<T>& g, void* out,
+                                      hipStream_t stream) {
+    const int tiles_x = (c.nx + kFzTx - 1) / kFzTx, tiles_y = (c.ny + kFzTy - 1) / kFzTy;
+    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    const int64_t nb = ntiles * ((c.nz + kFzZ - 1) / kFzZ);
+    if (nb > 0x7fffffff) return SVR_EUNSUPPORTED;
+    hipLaunchKernelGGL((smooth_fused_kernel<DT_IN, DT_OUT, T>), dim3((unsigned)nb), dim3(kBlock),
+                       0, stream, (const typename Elem<DT_IN>::T*)c.data,
+                       (typename Elem<DT_OUT>::T*)out, c.nx, c.ny, c.nz, tiles_x, (int)ntiles,
+                       (int)nb, g);
+    return hip_fail(hipGetLastError(), "smooth launch");
 }
 
 template <int T>
 static svr_status smooth_fixed(const svr_cube_view& c, const float* taps_host, void* out,
-                               float* w0, hipStream_t stream) {
+                               hipStream_t stream) {
     FixedTaps<T> g;
     for (int j = 0; j < T; ++j) g.g[j] = taps_host[j];
-    const int tiles_x = (c.nx + kXyTx - 1) / kXyTx, tiles_y = (c.ny + kXyTy - 1) / kXyTy;
-    const dim3 gxy((unsigned)((int64_t)tiles_x * tiles_y * c.nz));
     switch (c.dtype) {
-        case SVR_F16:
-            hipLaunchKernelGGL((smooth_xy_kernel<SVR_F16, T>), gxy, dim3(kBlock), 0, stream,
-                               (const _Float16*)c.data, w0, c.nx, c.ny, tiles_x, tiles_y, g);
-            break;
-        case SVR_BF16:
-            hipLaunchKernelGGL((smooth_xy_kernel<SVR_BF16, T>), gxy, dim3(kBlock), 0, stream,
-                               (const uint16_t*)c.data, w0, c.nx, c.ny, tiles_x, tiles_y, g);
-            break;
-        default:
-            hipLaunchKernelGGL((smooth_xy_kernel<SVR_F32, T>), gxy, dim3(kBlock), 0, stream,
-                               (const float*)c.data, w0, c.nx, c.ny, tiles_x, tiles_y, g);
+        case SVR_F16: return smooth_fused_launch<T, SVR_F16, SVR_F16>(c, g, out, stream);
+        case SVR_BF16: return smooth_fused_launch<T, SVR_BF16, SVR_BF16>(c, g, out, stream);
+        default: return smooth_fused_launch<T, SVR_F32, SVR_F32>(c, g, out, stream);
     }
-    const int64_t plane = (int64_t)c.nx * c.ny;
-    const int zblocks = (c.nz + kZR - 1) / kZR;
-    const int64_t nb = (plane + kBlock - 1) / kBlock * zblocks;
-    if (nb > 0x7fffffff) return SVR_EUNSUPPORTED;
-    const dim3 gz((unsigned)nb);
-    switch (c.dtype) {
-        case SVR_F16:
-            hipLaunchKernelGGL((smooth_z_kernel<SVR_F16, T>), gz, dim3(kBlock), 0, stream, w0,
-                               (_Float16*)out, plane, c.nz, zblocks, (int)nb, g);
-            break;
-        case SVR_BF16:
-            hipLaunchKernelGGL((smooth_z_kernel<SVR_BF16, T>), gz, dim3(kBlock), 0, stream, w0,
-                               (uint16_t*)out, plane, c.nz, zblocks, (int)nb, g);
-            break;
-        default:
-            hipLaunchKernelGGL((smooth_z_kernel<SVR_F32, T>), gz, dim3(kBlock), 0, stream, w0,
-                               (float*)out, plane, c.nz, zblocks, (int)nb, g);
-    }
-    return hip_fail(hipGetLastError(), "smooth launch");
 }
 
 svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int ntaps, void* out,
                          void* ws, hipStream_t stream) {
-    float* w0 = static_cast<float*>(ws);
     switch (ntaps) {
-        case 5: return smooth_fixed<5>(c, taps_host, out, w0, stream);
-        case 7: return smooth_fixed<7>(c, taps_host, out, w0, stream);
-        case 9: return smooth_fixed<9>(c, taps_host, out, w0, stream);
-        case 13: return smooth_fixed<13>(c, taps_host, out, w0, stream);
-        case 19: return smooth_fixed<19>(c, taps_host, out, w0, stream);
+        case 5: return smooth_fixed<5>(c, taps_host, out, stream);
+        case 7: return smooth_fixed<7>(c, taps_host, out, stream);
+        case 9: return smooth_fixed<9>(c, taps_host, out, stream);
+        case 13: return smooth_fixed<13>(c, taps_host, out, stream);
+        case 19: return smooth_fixed<19>(c, taps_host, out, stream);
         default: break;
     }
     return launch_smooth_generic(c, taps_host, ntaps, out, ws, stream);
