@@ -5,7 +5,7 @@ benchmark may import this package; the product (the HIP library and its binding)
 does, and this package never imports the product.  It is plain and slow on purpose.
 
 Contents
-  * ``render`` / ``render_grad`` / ``smooth`` / ``smooth_at`` / ``line_ratio``: ctypes
+  * ``render`` / ``render_grad`` / ``smooth`` / ``smooth_at`` / ``line_ratio`` / ``moments``: ctypes
     wrappers over ``oracle.c`` (double precision, one ray at a time).
   * ``taps``: binomial, Gaussian and the paper's linear-sampling 9-tap kernels.
   * ``quant``: float16 / bfloat16 round-to-nearest-even, finite min/max.
@@ -79,6 +79,9 @@ def lib():
         L.orc_line_ratio.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                      P(C.c_double)]
+        L.orc_moments.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_double, C.c_double, C.c_double, P(C.c_double),
+                                  P(C.c_double), P(C.c_int32)]
         L.orc_pixel_ray.argtypes = [P(_Camera), C.c_int32, C.c_int32, P(C.c_double),
                                     P(C.c_double)]
         L.orc_ray_box.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_double), P(C.c_double),
@@ -87,7 +90,7 @@ def lib():
                                     P(C.c_double)]
         L.orc_trilinear.restype = C.c_double
         for f in ("orc_render", "orc_render_grad", "orc_smooth", "orc_smooth_at",
-                  "orc_line_ratio", "orc_ray_box"):
+                  "orc_line_ratio", "orc_moments", "orc_ray_box"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -236,6 +239,21 @@ def line_ratio(cube, z0a, z0b, nzw, min_t_a=-np.inf, min_t_b=-np.inf, datamin=0.
                             float(datamin), _dp(out)) != 0:
         raise ValueError("orc_line_ratio rejected its arguments")
     return out
+
+
+def moments(cube, z0=0, nzw=None, dv=1.0, min_t=-np.inf, max_t=np.inf):
+    """Moment maps (Section 2.1, Eq. mom0 / Eq. mom1 and the argmax variant) of each spectrum
+    over channels [z0, z0 + nzw): (m0, m1, argmax), each [ny, nx]."""
+    V = _cube64(cube)
+    nz, ny, nx = V.shape
+    nzw = nz - z0 if nzw is None else nzw
+    m0 = np.empty((ny, nx))
+    m1 = np.empty((ny, nx))
+    am = np.empty((ny, nx), dtype=np.int32)
+    if lib().orc_moments(_dp(V), nx, ny, nz, z0, nzw, float(dv), float(min_t), float(max_t),
+                         _dp(m0), _dp(m1), am.ctypes.data_as(C.POINTER(C.c_int32))) != 0:
+        raise ValueError("orc_moments rejected its arguments")
+    return m0, m1, am
 
 
 def pixel_ray(camera, px, py):

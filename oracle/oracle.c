@@ -669,3 +669,32 @@ int orc_line_ratio(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t 
         }
     return 0;
 }
+
+/* Section 2.1: the zeroth moment integrates each spectrum (Eq. mom0, the channel sum times the
+ * channel width), the first moment is its intensity-weighted mean channel (Eq. mom1), and the
+ * argmax variant returns the channel of the spectrum's maximum.  Readings: channels that are
+ * not finite or fall outside [min_t, max_t] do not count (like clipped samples); ties in the
+ * maximum go to the later channel, as in the MIP rule of Eq. MIP (v_i >= c_{i-1}). */
+int orc_moments(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t z0, int32_t nzw,
+                double dv, double min_t, double max_t, double* m0, double* m1, int32_t* amax) {
+    if (!V || !m0 || !m1 || !amax || nzw < 1 || z0 < 0 || z0 + nzw > nz) return 1;
+    const int64_t plane = (int64_t)nx * ny;
+    for (int64_t i = 0; i < plane; ++i) {
+        double s0 = 0.0, s1 = 0.0, best = 0.0;
+        int32_t arg = -1;
+        for (int32_t z = z0; z < z0 + nzw; ++z) {
+            const double v = V[z * plane + i];
+            if (!isfinite(v) || v < min_t || v > max_t) continue;
+            s0 += v;
+            s1 += (double)z * v;
+            if (arg < 0 || v >= best) {
+                best = v;
+                arg = z;
+            }
+        }
+        m0[i] = dv * s0;
+        m1[i] = (arg >= 0 && s0 != 0.0) ? s1 / s0 : NAN;
+        amax[i] = arg;
+    }
+    return 0;
+}

@@ -114,6 +114,14 @@ int orc_line_ratio(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t 
                    int32_t z0b, int32_t nzw, double min_t_a, double min_t_b, double datamin,
                    double* out);
 
+/* Moment maps of every spectrum over channels [z0, z0 + nzw) (Section 2.1, Eq. mom0 and
+ * Eq. mom1, and the argmax variant).  A channel counts when its value is finite and inside
+ * [min_t, max_t].  m0 = dv * sum v; m1 = sum z v / sum v with z the cube's channel index (NaN
+ * when no channel counts or the sum is zero); amax = the last channel holding the largest
+ * counted value (-1 when none counts).  Outputs [ny][nx]. */
+int orc_moments(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t z0, int32_t nzw,
+                double dv, double min_t, double max_t, double* m0, double* m1, int32_t* amax);
+
 #ifdef __cplusplus
 }
 #endif

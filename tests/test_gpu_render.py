@@ -122,11 +122,13 @@ def test_opacity_from_table_and_auto_clim(svr, ragged):
     assert err <= TOL32
 
 
-def test_brick16_equals_brick8(svr, ragged):
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_brick16_equals_brick8(svr, ragged, storage):
+    """Renders do not depend on the brick edge (FP32 plain bricks, 16-bit y-pair bricks)."""
     cube, lo, hi, cam = ragged
     lut = to_cuda(synth.lut_heat(256))
-    a = _vol(svr, cube, brick=8)
-    b = _vol(svr, cube, brick=16)
+    a = _vol(svr, cube, storage, brick=8)
+    b = _vol(svr, cube, storage, brick=16)
     for mode in MODES:
         ia = svr.svr_render(a, cam, lut, mode=mode, clim_lo=lo, clim_hi=hi)
         ib = svr.svr_render(b, cam, lut, mode=mode, clim_lo=lo, clim_hi=hi)

@@ -557,3 +557,74 @@ def test_finite_minmax_ignores_nan():
     lo, hi = quant.finite_minmax(cube)
     f = cube[np.isfinite(cube)]
     assert lo == f.min() and hi == f.max() and np.isnan(cube).any()
+
+
+# ------------------------------------------------------------------ moment maps (Section 2.1)
+def _gauss_line_cube(nx, ny, nz, seed):
+    """Each spectrum one Gaussian line A exp(-(z - mu)^2 / 2 s^2), s = 3 channels, with mu at
+    least 10 s from both ends: the channel sums equal the integrals up to terms below 1e-20
+    (Poisson summation), so M0 = dv A s sqrt(2 pi) and M1 = mu."""
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(0.5, 4.0, (ny, nx))
+    mu = rng.uniform(31.0, nz - 31.0, (ny, nx))
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    s = 3.0
+    return amp * np.exp(-(z - mu[None]) ** 2 / (2 * s * s)), amp, mu, s
+
+
+def test_moments_gaussian_line_closed_form():
+    V, amp, mu, s = _gauss_line_cube(7, 5, 96, 0)
+    dv = 2.5
+    m0, m1, am = oracle.moments(V, dv=dv)
+    assert np.max(np.abs(m0 / (dv * amp * s * math.sqrt(2 * math.pi)) - 1.0)) < 1e-12
+    assert np.max(np.abs(m1 - mu)) < 1e-10
+    # the peak channel is the channel nearest to mu (mu is never within 1e-3 of a half-integer
+    # for this seed, checked here)
+    assert np.min(np.abs(mu - np.floor(mu) - 0.5)) > 1e-3
+    assert np.array_equal(am, np.rint(mu).astype(np.int32))
+
+
+def test_moments_window_uses_absolute_channel():
+    """A window holding the whole line gives the same moments as the full spectrum; M1 is a
+    channel index of the cube, not of the window."""
+    V, amp, mu, s = _gauss_line_cube(4, 3, 128, 1)
+    mu_lo, mu_hi = int(mu.min()), int(mu.max())
+    z0 = max(0, mu_lo - 40)
+    nzw = min(128, mu_hi + 40) - z0
+    full = oracle.moments(V)
+    win = oracle.moments(V, z0=z0, nzw=nzw)
+    assert np.max(np.abs(win[0] - full[0])) < 1e-12 * np.max(np.abs(full[0]))
+    assert np.max(np.abs(win[1] - full[1])) < 1e-10
+    assert np.array_equal(win[2], full[2])
+
+
+def test_moments_ties_symmetry_and_exclusions():
+    # plateau maximum: the later channel (MIP's >= rule); symmetric spectrum: M1 at the centre
+    V = np.zeros((6, 1, 1))
+    V[:, 0, 0] = [0.0, 1.0, 3.0, 3.0, 1.0, 0.0]
+    m0, m1, am = oracle.moments(V)
+    assert m0[0, 0] == 8.0 and m1[0, 0] == 2.5 and am[0, 0] == 3
+    # non-finite channels and channels outside [min_t, max_t] do not count
+    V = np.zeros((6, 1, 1))
+    V[:, 0, 0] = [1.0, 2.0, np.nan, 5.0, 100.0, -np.inf]
+    m0, m1, am = oracle.moments(V, dv=0.5, min_t=-1.0, max_t=10.0)
+    assert m0[0, 0] == 0.5 * 8.0
+    assert abs(m1[0, 0] - (0 * 1 + 1 * 2 + 3 * 5) / 8.0) < 1e-15
+    assert am[0, 0] == 3
+    # nothing counts: M0 = 0, M1 undefined, no argmax; a zero sum leaves M1 undefined too
+    V = np.full((4, 1, 2), np.nan)
+    V[:, 0, 1] = [1.0, -1.0, 2.0, -2.0]
+    m0, m1, am = oracle.moments(V)
+    assert m0[0, 0] == 0.0 and np.isnan(m1[0, 0]) and am[0, 0] == -1
+    assert m0[0, 1] == 0.0 and np.isnan(m1[0, 1]) and am[0, 1] == 2
+
+
+def test_moments_linearity():
+    """M0 scales with the data, M1 and the argmax do not; both are independent per spectrum."""
+    rng = np.random.default_rng(3)
+    V = rng.uniform(0.1, 1.0, (20, 3, 4))
+    a = oracle.moments(V, dv=1.5)
+    b = oracle.moments(3.0 * V, dv=1.5)
+    assert np.max(np.abs(b[0] - 3.0 * a[0])) < 1e-12 * np.max(b[0])
+    assert np.max(np.abs(b[1] - a[1])) < 1e-12 * np.max(a[1])
+    assert np.array_equal(a[2], b[2])
