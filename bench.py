@@ -57,12 +57,13 @@ KERNEL_SOURCES = {
     "line_ratio": ("common.h", "smooth.hip"),
     "upload": ("common.h", "volume.hip"),
     "train": ("common.h", "sampler.h", "train.hip"),
+    "moments": ("common.h", "moments.hip"),
     "copy": (),
 }
 
 
 def kernel_family(kernel):
-    for fam in ("render", "smooth", "line_ratio", "upload", "train", "copy"):
+    for fam in ("render", "smooth", "line_ratio", "upload", "train", "moments", "copy"):
         if kernel.startswith(fam):
             return fam
     raise KeyError(kernel)
@@ -91,7 +92,7 @@ def parse():
     ap.add_argument("--profile", default=None,
                     help="run only this kernel on the main workload, --steps times (for "
                          "rocprofv3): render_<mode>, render_sparse, smooth_sigma<s>, upload, "
-                         "line_ratio, train_fwd, train_bwd, copy (a 1 GiB device copy used to "
+                         "line_ratio, moments, train_fwd, train_bwd, copy (a 1 GiB device copy used to "
                          "scale the counters)")
     return ap.parse_args()
 
@@ -338,6 +339,9 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
         fn = lambda: svr.svr_volume_upload(vol, cube)  # noqa: E731
     elif name == "line_ratio":
         fn = lambda: svr.svr_line_ratio(cube, 400, 600, 32, 3.0, 3.0, lo, out=ratio_out)  # noqa: E731,E501
+    elif name == "moments":
+        mom = svr.svr_moments(cube)
+        fn = lambda: svr.svr_moments(cube, out=mom)  # noqa: E731
     elif name in ("train_fwd", "train_bwd"):
         # the differentiable form: 256^3 cube, 1024x1024, 64-point transfer function
         c4 = torch.from_numpy(synth.cfg4_cube(0)).cuda()
@@ -407,6 +411,14 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
                                 hbm_bytes_algorithmic=nbytes,
                                 gbps=nbytes / (ms * 1e-3) / 1e9,
                                 hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM)
+    # moment maps M0 / M1 / argmax over the whole spectral axis: one streaming read of the cube
+    log("form: moment maps")
+    mom = svr.svr_moments(cube)
+    ms = _time(torch, lambda: svr.svr_moments(cube, out=mom), 10)
+    nbytes = 4 * cube.numel() + 12 * cube.shape[1] * cube.shape[2]
+    forms["moments"] = dict(ms=ms, hbm_bytes_algorithmic=nbytes,
+                            gbps=nbytes / (ms * 1e-3) / 1e9,
+                            hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM)
     # float16 / bfloat16 storage (FP32 arithmetic)
     for st in ("f16", "bf16"):
         log(f"form: {st} storage")

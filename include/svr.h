@@ -173,6 +173,23 @@ svr_status svr_smooth_workspace(const svr_cube_view* in, size_t* bytes);
 svr_status svr_smooth(const svr_cube_view* in, const float* taps_host, int32_t ntaps,
                       void* out, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- moment maps
+ * Moment maps of every spectrum of a cube over the channel window [z0, z0 + nz_w)
+ * (Section 2.1, Eq. mom0 and Eq. mom1, and the argmax variant described with them).  A
+ * channel counts when its value is finite and inside [min_t, max_t] (pass -inf / +inf for
+ * no clipping).  For the spectrum at (x, y):
+ *   m0_out[y][x]     = dv * sum of the counted values (dv: channel width);
+ *   m1_out[y][x]     = sum z v / sum v over the counted channels, z the cube's channel index
+ *                      (NaN when no channel counts or the sum is zero);
+ *   argmax_out[y][x] = the last channel holding the largest counted value (the MIP tie rule),
+ *                      -1 when no channel counts.
+ * Sums are formed in float64 in channel order and rounded to float32 at the end.  Outputs are
+ * C-contiguous [ny][nx] device buffers owned by the caller; any of them may be NULL, not all.
+ * SVR_EINVAL: window outside the cube, NaN dv / min_t / max_t, min_t > max_t, ny > 65535. */
+svr_status svr_moments(const svr_cube_view* cube, int32_t z0, int32_t nz_w, float dv,
+                       float min_t, float max_t, float* m0_out, float* m1_out,
+                       int32_t* argmax_out, void* stream);
+
 /* ---------------------------------------------------------------- line ratio pass
  * Voxel-wise emission-line ratio of two spectral windows of one cube (Section 4.5,
  * method 2 computed per voxel): with a = cube[z0_a + j], b = cube[z0_b + j] (j < nz_w),

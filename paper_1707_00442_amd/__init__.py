@@ -5,7 +5,7 @@ Every step of the rendering, smoothing, line-ratio, adjoint and batched paths ru
 hand-written HIP kernels of libsvr.so; PyTorch supplies device memory and streams.  There
 is no CPU fallback: if the library is missing, importing the functions raises.
 
-Functions keep the C names (svr_render, svr_smooth, svr_line_ratio, ...).  Tensors are
+Functions keep the C names (svr_render, svr_smooth, svr_line_ratio, svr_moments, ...).  Tensors are
 CUDA (HIP) tensors, cubes are [z][y][x] (x = RA fastest, y = Dec, z = velocity).
 """
 from __future__ import annotations
@@ -249,6 +249,24 @@ def svr_line_ratio(cube, z0_a, z0_b, nz_w, min_t_a=-math.inf, min_t_b=-math.inf,
     _check(lib().svr_line_ratio(C.byref(v), int(z0_a), int(z0_b), int(nz_w), float(min_t_a),
                                 float(min_t_b), float(datamin), C.c_void_p(out.data_ptr()),
                                 _stream(stream)), "svr_line_ratio")
+    return out
+
+
+def svr_moments(cube, z0=0, nz_w=None, dv=1.0, min_t=-math.inf, max_t=math.inf, out=None,
+                stream=None):
+    """Moment maps of every spectrum over channels [z0, z0 + nz_w): (m0, m1, argmax), float32,
+    float32 and int32 tensors of shape [ny, nx] (out: an optional triple of such tensors)."""
+    v = cube_view(cube)
+    nz, ny, nx = cube.shape
+    nz_w = nz - z0 if nz_w is None else nz_w
+    if out is None:
+        out = (torch.empty((ny, nx), dtype=torch.float32, device="cuda"),
+               torch.empty((ny, nx), dtype=torch.float32, device="cuda"),
+               torch.empty((ny, nx), dtype=torch.int32, device="cuda"))
+    ptr = [C.c_void_p(t.data_ptr()) if t is not None else None for t in out]
+    _check(lib().svr_moments(C.byref(v), int(z0), int(nz_w), float(dv), float(min_t),
+                             float(max_t), ptr[0], ptr[1], ptr[2], _stream(stream)),
+           "svr_moments")
     return out
 
 

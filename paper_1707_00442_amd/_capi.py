@@ -22,7 +22,7 @@ EXPORTS = (
     "svr_volume_clim",
     "svr_volume_export", "svr_params_validate", "svr_render", "svr_smooth_workspace",
     "svr_smooth",
-    "svr_line_ratio", "svr_render_train_workspace", "svr_render_train",
+    "svr_line_ratio", "svr_moments", "svr_render_train_workspace", "svr_render_train",
     "svr_render_backward", "svr_batch_create", "svr_batch_launch", "svr_batch_info",
     "svr_batch_destroy", "svr_sync",
 )
@@ -83,6 +83,7 @@ def load():
         "svr_smooth_workspace": (C.c_int, [P(CubeView), P(C.c_size_t)]),
         "svr_smooth": (C.c_int, [P(CubeView), P(f32), i32, vp, vp, C.c_size_t, vp]),
         "svr_line_ratio": (C.c_int, [P(CubeView), i32, i32, i32, f32, f32, f32, vp, vp]),
+        "svr_moments": (C.c_int, [P(CubeView), i32, i32, f32, f32, f32, vp, vp, vp, vp]),
         "svr_render_train_workspace": (C.c_int, [vp, P(Camera), P(Params), P(C.c_size_t)]),
         "svr_render_train": (C.c_int, [vp, P(Camera), P(Lut), P(Params), vp, vp, C.c_size_t,
                                        vp]),

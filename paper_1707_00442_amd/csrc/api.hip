@@ -38,6 +38,8 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
                          int32_t* samples, hipStream_t stream);
 svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int ntaps, void* out,
                          void* ws, hipStream_t stream);
+svr_status launch_moments(const svr_cube_view& c, int z0, int nzw, float dv, float lo, float hi,
+                          float* m0, float* m1, int32_t* amax, hipStream_t stream);
 svr_status launch_line_ratio(const svr_cube_view& c, int z0a, int z0b, int nzw, float min_a,
                              float min_b, float datamin, float* out, hipStream_t stream);
 
@@ -331,6 +333,22 @@ svr_status svr_line_ratio(const svr_cube_view* cube, int32_t z0_a, int32_t z0_b,
     SVR_CHECK(ratio_out != nullptr, "svr_line_ratio: null output");
     return launch_line_ratio(*cube, z0_a, z0_b, nz_w, min_t_a, min_t_b, datamin, ratio_out,
                              S(stream));
+}
+
+svr_status svr_moments(const svr_cube_view* cube, int32_t z0, int32_t nz_w, float dv,
+                       float min_t, float max_t, float* m0_out, float* m1_out,
+                       int32_t* argmax_out, void* stream) {
+    svr_status st = check_view(cube, "svr_moments");
+    if (st) return st;
+    SVR_CHECK(nz_w >= 1 && z0 >= 0 && (int64_t)z0 + nz_w <= cube->nz,
+              "svr_moments: window [%d, %d) outside 0..%d", z0, z0 + nz_w, cube->nz);
+    SVR_CHECK(cube->ny <= 65535, "svr_moments: ny too large for the launch grid");
+    SVR_CHECK(!isnan(dv) && !isnan(min_t) && !isnan(max_t), "svr_moments: NaN argument");
+    SVR_CHECK(min_t <= max_t, "svr_moments: min_t %g > max_t %g", (double)min_t, (double)max_t);
+    SVR_CHECK(m0_out != nullptr || m1_out != nullptr || argmax_out != nullptr,
+              "svr_moments: no output");
+    return launch_moments(*cube, z0, nz_w, dv, min_t, max_t, m0_out, m1_out, argmax_out,
+                          S(stream));
 }
 
 svr_status svr_sync(void* stream) {

@@ -124,3 +124,19 @@ def test_status_strings(capi):
     L = capi.load()
     for s in range(5):
         assert L.svr_status_string(s).startswith(b"SVR_")
+
+
+def test_moments_validation(capi):
+    """svr_moments rejects bad windows and arguments on the host (fake device pointers are
+    never touched)."""
+    L = capi.load()
+    v = C.byref(_fake_view(capi))
+    p = C.c_void_p(0x2000)
+    inf = math.inf
+    assert L.svr_moments(v, 0, 9, 1.0, -inf, inf, p, p, p, None) == capi.SVR_EINVAL  # nz = 8
+    assert L.svr_moments(v, -1, 4, 1.0, -inf, inf, p, p, p, None) == capi.SVR_EINVAL
+    assert L.svr_moments(v, 0, 0, 1.0, -inf, inf, p, p, p, None) == capi.SVR_EINVAL
+    assert L.svr_moments(v, 0, 8, math.nan, -inf, inf, p, p, p, None) == capi.SVR_EINVAL
+    assert L.svr_moments(v, 0, 8, 1.0, 2.0, 1.0, p, p, p, None) == capi.SVR_EINVAL
+    assert L.svr_moments(v, 0, 8, 1.0, -inf, inf, None, None, None, None) == capi.SVR_EINVAL
+    assert b"svr_moments" in L.svr_last_error()
