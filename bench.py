@@ -89,6 +89,10 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--protocol", action="store_true",
+                    help="instead of the step: the paper's frame-rate protocol (uniform [0,1] "
+                         "cubes 128^3..1024^3, raw and box 3..11, MIP0 and AVIP0, median fps "
+                         "over a full rotation x3 at 1000x1000, and the canvas sweep)")
     ap.add_argument("--profile", default=None,
                     help="run only this kernel on the main workload, --steps times (for "
                          "rocprofv3): render_<mode>, render_sparse, smooth_sigma<s>, upload, "
@@ -157,6 +161,8 @@ def main():
 
     torch.cuda.set_device(0)
     svr.lib()
+    if args.protocol:
+        return run_protocol(torch, svr, synth)
     t_setup = time.time()
     nx, ny, nz = 512, 512, 1024
     W, H = 1920, 1080
@@ -306,6 +312,57 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cube_np, views[Wu], synth, lo, hi, args)
     log(f"total {time.time() - t_setup:.1f}s")
     print(json.dumps(out), flush=True)
+
+
+def run_protocol(torch, svr, synth, sizes=(128, 256, 512, 1024), canvas=1000, reps=3):
+    """The paper's frame-rate benchmark (Section 6, Appendix B) on this GPU: uniform [0, 1)
+    float32 cubes, one sample per voxel (dt = 1), the rotation views (10 degree steps), each
+    frame timed on its own; fps = 1000 / median frame time over `reps` full rotations.
+    Kernels: raw and box smoothing of 3..11 samples (filterArm 1..5); MIP0, and AVIP0 with
+    k = 0.22 and clipping at minThreshold = 0.9 (the paper's settings).  Canvas sweep: MIP0 raw
+    at 500^2 .. 2000^2."""
+    lut = torch.from_numpy(synth.lut_heat(256)).cuda()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def median_fps(vol, views, p, out):
+        ms = []
+        for _ in range(reps):
+            for cam in views:
+                e0.record()
+                svr.svr_render(vol, cam, lut, p, out=out)
+                e1.record()
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+        return 1e3 / float(np.median(ms))
+
+    res = {"fps": {}, "canvas": {}}
+    for n in sizes:
+        log(f"protocol: {n}^3 uniform cube")
+        cube = torch.from_numpy(synth.uniform_cube(n, seed=0)).cuda()
+        lo, hi = svr.svr_minmax(cube)
+        vol = svr.svr_volume_create(cube)
+        del cube
+        views = [v.as_f32() for v in synth.rotation_views(n, n, n, canvas, canvas)]
+        out = torch.empty((canvas, canvas, 4), dtype=torch.float32, device="cuda")
+        for mode in ("mip0", "avip0"):
+            for arm in range(6):
+                p = dict(mode=mode, k=0.22, dt=1.0, box_arm=arm, clim_lo=lo, clim_hi=hi)
+                if mode == "avip0":
+                    p.update(filter="clip", min_t=0.9)
+                svr.svr_render(vol, views[0], lut, p, out=out)
+                name = "raw" if arm == 0 else f"box{2 * arm + 1}"
+                res["fps"][f"{n}^3 {mode} {name}"] = round(median_fps(vol, views, p, out), 1)
+        for cv in (500, 1000, 1500, 2000):
+            cviews = [v.as_f32() for v in synth.rotation_views(n, n, n, cv, cv)]
+            cout = torch.empty((cv, cv, 4), dtype=torch.float32, device="cuda")
+            p = dict(mode="mip0", dt=1.0, clim_lo=lo, clim_hi=hi)
+            svr.svr_render(vol, cviews[0], lut, p, out=cout)
+            res["canvas"][f"{n}^3 {cv}x{cv}"] = round(median_fps(vol, cviews, p, cout), 1)
+        vol.close()
+        log(f"protocol: {n}^3 done")
+    print(json.dumps({"protocol": "paper frame-rate benchmark (uniform cubes, dt = 1, "
+                                  "rotation median x3)", "canvas_px": canvas, **res}),
+          flush=True)
 
 
 def sparse_camera(synth):

@@ -95,6 +95,29 @@ def test_all_modes_filters_box(svr, ragged, mode, filt, box):
     assert hit > 2000
 
 
+@pytest.mark.parametrize("mode", ["mip0", "avip0"])
+@pytest.mark.parametrize("box", [0, 5])
+def test_frame_rate_protocol_configuration(svr, mode, box):
+    """The settings of the paper's frame-rate benchmark (bench.py --protocol): a uniform
+    [0, 1) cube, one sample per voxel (dt = 1), rotation views, MIP0, and AVIP0 with k = 0.22
+    clipped at minThreshold = 0.9, raw and box 11 (filterArm 5); whole frame against the oracle."""
+    cube = synth.uniform_cube(64, seed=0)
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.rotation_views(64, 64, 64, 120, 120)[4].as_f32()
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, k=0.22, dt=1.0, box_arm=box)
+    if mode == "avip0":
+        params.update(filter="clip", min_t=0.9)
+    print(f"[protocol] mode={mode} box={box}", flush=True)
+    got, ns = gpu_render(svr, _vol(svr, cube), cam, to_cuda(lut), params, lo, hi)
+    err, frag, _ = compare_render(oracle, got, ns, cube, cam, lut, params, lo, hi,
+                                  margins=margins(lo, hi, params), cond_tol=COND_TOL)
+    hit = int((ns > 0).sum())
+    print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
+    assert err <= TOL32
+    assert frag.sum() < 0.05 * hit and hit > 5000
+
+
 @pytest.mark.parametrize("mode", ["mip0", "mip1", "miprgb"])
 @pytest.mark.parametrize("mip_alpha", [1, 2])
 def test_mip_alpha_modes(svr, ragged, mode, mip_alpha):
