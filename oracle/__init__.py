@@ -40,7 +40,9 @@ class _Params(C.Structure):
                 ("lo", C.c_double), ("hi", C.c_double), ("dt", C.c_double),
                 ("min_t", C.c_double), ("max_t", C.c_double),
                 ("min_t2", C.c_double), ("max_t2", C.c_double),
-                ("ratio_lo", C.c_double), ("ratio_hi", C.c_double)]
+                ("ratio_lo", C.c_double), ("ratio_hi", C.c_double),
+                ("star_n", C.c_int32), ("star_c0", C.c_double),
+                ("star_off", C.c_double * 4), ("star_w", C.c_double * 4)]
 
 
 class _Margins(C.Structure):
@@ -133,6 +135,14 @@ def params_struct(params):
     for name in ("k", "min_val", "ert", "lo", "hi", "dt", "min_t", "max_t", "min_t2",
                  "max_t2", "ratio_lo", "ratio_hi"):
         setattr(p, name, float(q[name]))
+    # in-ray Gaussian (Section 4.2): star = (c0, [(off_1, w_1), ...]) or None
+    if q.get("star"):
+        c0, pairs = q["star"]
+        p.star_n = len(pairs)
+        p.star_c0 = float(c0)
+        for i, (o, w) in enumerate(pairs):
+            p.star_off[i] = float(o)
+            p.star_w[i] = float(w)
     return p
 
 

@@ -145,15 +145,38 @@ static void ray_loc(const ray_ctx* r, int64_t k, double loc[3]) {
     loc[2] = clampd((q[2] + 0.5) / r->nz, 0.0, 1.0);
 }
 
+/* Section 4.2's in-shader Gaussian at point q (Alg. 9-tap smoothing, applied to each data
+ * axis in turn, x then y then z): smooth(oVal, direction) = oVal c0 + sum over the offset
+ * pairs of w_k (cube[q + off_k e] + cube[q - off_k e]), in the printed order; the result of
+ * one axis is the oVal of the next.  Every lookup is the trilinear fetch of the raw cube. */
+static double star_sample(const ray_ctx* r, const double* V, const double q[3]) {
+    const orc_params* p = r->p;
+    double val = orc_trilinear(V, r->nx, r->ny, r->nz, q);
+    for (int a = 0; a < 3; ++a) {
+        double acc = 0.0;
+        acc = acc + val * p->star_c0;
+        for (int k = 0; k < p->star_n; ++k) {
+            double qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
+            qp[a] += p->star_off[k];
+            qm[a] -= p->star_off[k];
+            acc = acc + orc_trilinear(V, r->nx, r->ny, r->nz, qp) * p->star_w[k];
+            acc = acc + orc_trilinear(V, r->nx, r->ny, r->nz, qm) * p->star_w[k];
+        }
+        val = acc;
+    }
+    return val;
+}
+
 /* cube[loc] followed by smooth() of Alg. 1: the box mean of the 2a+1 samples taken at the
- * ray's own positions k-a .. k+a (Section 4.1, "along the ray direction"). */
+ * ray's own positions k-a .. k+a (Section 4.1, "along the ray direction"), or the in-ray
+ * Gaussian of Section 4.2. */
 static double ray_sample(const ray_ctx* r, const double* V, int64_t k, int which) {
     double q[3];
     ray_point(r, k, q);
     if (r->pert && r->mg->pp > 0.0)
         for (int a = 0; a < 3; ++a)
             q[a] += r->mg->pp * (fabs(q[a]) + 1.0) * probe_sign(r->pix, k, 16 * r->pert + 4 + a);
-    double v = orc_trilinear(V, r->nx, r->ny, r->nz, q);
+    double v = r->p->star_n > 0 ? star_sample(r, V, q) : orc_trilinear(V, r->nx, r->ny, r->nz, q);
     if (r->pert == 1) v += r->mg->pv;  /* correlated error: every sample moved up */
     if (r->pert == 2) v += r->mg->pv * probe_sign(r->pix, k, 16 + which);  /* random signs */
     if (r->pert == 3) v += which ? -r->mg->pv : r->mg->pv;  /* the two cubes move apart */
@@ -404,6 +427,8 @@ static int check_common(int32_t nx, int32_t ny, int32_t nz, const orc_camera* ca
     if (M < 2 || !p || !(p->dt > 0.0)) return 1;
     if (p->mode < 0 || p->mode > ORC_AVIPRGB) return 1;
     if (p->ratio && (p->box_arm != 0 || p->mode != ORC_MIP0)) return 1;
+    if (p->star_n < 0 || p->star_n > 4) return 1;
+    if (p->star_n > 0 && (p->box_arm != 0 || p->ratio)) return 1;
     return 0;
 }
 
@@ -489,7 +514,8 @@ int orc_render_grad(const double* V, int32_t nx, int32_t ny, int32_t nz,
                     int64_t npix, const int64_t* pix, const double* grad_rgba,
                     double* rgba, double* grad_tf, double* grad_vox) {
     if (!V || check_common(nx, ny, nz, cam, M, p) || !tf || !grad_rgba || !rgba) return 1;
-    if (p->mode != ORC_AVIP0 || p->filter != ORC_FILTER_NONE || p->box_arm != 0 || p->ratio)
+    if (p->mode != ORC_AVIP0 || p->filter != ORC_FILTER_NONE || p->box_arm != 0 || p->ratio ||
+        p->star_n != 0)
         return 1;
     const int64_t npx = (int64_t)cam->width * cam->height;
     if (!pix) npix = npx;

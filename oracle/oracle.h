@@ -44,6 +44,14 @@ typedef struct {
     double min_t, max_t;      /* thresholds (cube 1 for the ratio methods) */
     double min_t2, max_t2;    /* thresholds for cube 2 (ratio methods) */
     double ratio_lo, ratio_hi;/* domain the ratio is normalised over */
+    /* In-ray 3-axis Gaussian of Section 4.2 (Alg. 9-tap smoothing), star_n > 0 to enable:
+     * the one-axis stencil c0 v + sum_k w_k (cube[p + off_k e] + cube[p - off_k e]) applied
+     * along x, then y, then z, each axis taking the previous result as its centre value.
+     * PARITY UNPINNED in general (how the paper combines the three axes is a reading); the
+     * one-axis reductions are pinned. */
+    int32_t star_n;           /* number of (off, w) pairs, 0..4 */
+    double star_c0;
+    double star_off[4], star_w[4];
 } orc_params;
 
 /* Margins below which a discrete decision counts as "could flip" (fragile pixel). */

@@ -628,3 +628,84 @@ def test_moments_linearity():
     assert np.max(np.abs(b[0] - 3.0 * a[0])) < 1e-12 * np.max(b[0])
     assert np.max(np.abs(b[1] - a[1])) < 1e-12 * np.max(a[1])
     assert np.array_equal(a[2], b[2])
+
+
+# ------------------------------------------------------------------ in-ray Gaussian (Section 4.2)
+# The paper's 9-tap stencil: centre weight and (offset, weight) pairs (golden constants).
+STAR9 = (taps.PAPER9_CENTRE_WEIGHT, taps.PAPER9_PAIRS)
+
+
+def _axis_view_red(cube, axis, star):
+    """MIP0 through the two-entry grey table [0, 1], parallel rays along `axis` through voxel
+    centres:
+    every sample of a ray shares the two other coordinates, and on a cube that varies only
+    across the ray the rendered value is the smoothed value itself."""
+    nz, ny, nx = cube.shape
+    n = {"x": nx, "y": ny, "z": nz}
+    others = [a for a in "xyz" if a != axis]
+    cam = synth.ortho_axis(nx, ny, nz, n[others[0]], n[others[1]], "+" + axis)
+    lo, hi = float(cube.min()), float(cube.max())
+    p = dict(mode="mip0", lo=lo - 1.0, hi=hi + 1.0, dt=0.5, star=star)
+    ramp = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 1.0, 1.0, 1.0]])  # red = s exactly
+    rgba, frag, ns = oracle.render(cube, cam, ramp, p)
+    s = rgba[:, 0].reshape(n[others[1]], n[others[0]])
+    return s * (p["hi"] - p["lo"]) + p["lo"]
+
+
+def _interp_clamped(f, t):
+    return np.interp(t, np.arange(f.size, dtype=np.float64), f)
+
+
+def _one_axis(f, t, c0, pairs):
+    """c0 f(t) + sum_k w_k (f(t + o_k) + f(t - o_k)) on the clamped linear interpolant of f."""
+    out = c0 * _interp_clamped(f, t)
+    for o, w in pairs:
+        out = out + w * (_interp_clamped(f, t + o) + _interp_clamped(f, t - o))
+    return out
+
+
+def test_star_weights_sum_to_one_and_constant_cube():
+    c0, pairs = STAR9
+    assert abs(c0 + 2 * sum(w for _, w in pairs) - 1.0) < 1e-9
+    cube = np.full((12, 10, 9), 3.25)
+    v = _axis_view_red(cube, "z", STAR9)
+    assert np.max(np.abs(v - 3.25)) < 1e-8
+
+
+def test_star_reduces_to_one_axis_filter():
+    """On a cube that varies along one axis only, the stencils of the other two axes see a
+    constant and the result has a closed form: along z (the last axis) the 1D stencil itself;
+    along y, c0 F + (1 - c0) f; along x, c0^2 F + (1 - c0^2) f (F the 1D stencil, f the
+    value), since each later axis takes the earlier result as its centre and fetches the raw
+    cube around it."""
+    c0, pairs = STAR9
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(17)
+    t = np.arange(17, dtype=np.float64)
+    F = _one_axis(f, t, c0, pairs)
+    # varies along z, rays along x: image rows are z
+    cube = np.broadcast_to(f[:, None, None], (17, 6, 5)).copy()
+    v = _axis_view_red(cube, "x", STAR9)
+    assert np.max(np.abs(v - F[:, None])) < 1e-9
+    # varies along y, rays along z: image rows are y
+    cube = np.broadcast_to(f[None, :, None], (6, 17, 5)).copy()
+    v = _axis_view_red(cube, "z", STAR9)
+    assert np.max(np.abs(v - (c0 * F + (1 - c0) * f)[:, None])) < 1e-9
+    # varies along x, rays along z: image columns are x
+    cube = np.broadcast_to(f[None, None, :], (6, 5, 17)).copy()
+    v = _axis_view_red(cube, "z", STAR9)
+    assert np.max(np.abs(v - (c0 * c0 * F + (1 - c0 * c0) * f)[None, :])) < 1e-9
+
+
+def test_star_linear_sampling_at_voxel_centres():
+    """At voxel centres the 9-tap stencil of fractional offsets equals the discrete 9-tap
+    filter of the paper's taps (the linear-sampling identity of the printed constants)."""
+    g = taps.paper9()
+    assert g.size == 9
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal(30)
+    c0, pairs = STAR9
+    t = np.arange(4, 26, dtype=np.float64)
+    F = _one_axis(f, t, c0, pairs)
+    direct = np.array([sum(g[j] * f[int(ti) + j - 4] for j in range(9)) for ti in t])
+    assert np.max(np.abs(F - direct)) < 1e-9
