@@ -468,6 +468,17 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
                                 hbm_bytes_algorithmic=nbytes,
                                 gbps=nbytes / (ms * 1e-3) / 1e9,
                                 hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM)
+    # the paper's in-ray 9-tap Gaussian (13 trilinear fetches per sample), view 0
+    star9 = (0.2270270270, [(1.3846153846, 0.3162162162), (3.2307692308, 0.0702702703)])
+    r = {}
+    for m in ("mip0", "avip0"):
+        ps = dict(params[m], star=star9)
+        _, ns = svr.svr_render(vol32, cam, lut, ps, samples=True)
+        n = int(ns.sum().item())
+        ms = _time(torch, lambda: svr.svr_render(vol32, cam, lut, ps), 3)
+        r[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fetches_per_s=13 * n / (ms * 1e-3),
+                    fps=1e3 / ms)
+    forms["star9_in_ray_gaussian"] = r
     # moment maps M0 / M1 / argmax over the whole spectral axis: one streaming read of the cube
     log("form: moment maps")
     mom = svr.svr_moments(cube)

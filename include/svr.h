@@ -115,6 +115,8 @@ typedef struct {
     int32_t n;
 } svr_lut;
 
+#define SVR_MAX_STAR 4
+
 /* Parameters of Alg. 1 and its smooth()/filter()/transferFunction()/setFragment().
  *  mode            svr_mode.
  *  filter          svr_filter, thresholds min_t/max_t (Sections 4.3, 4.4); for the ratio
@@ -134,7 +136,16 @@ typedef struct {
  *  clim_lo/hi      colour-map domain [lo, hi]; DATAMIN = lo.  clim_hi <= clim_lo selects
  *                  the volume's own finite min/max.
  *  dt              sample spacing along the ray, voxels (> 0).  Samples t_k = t_enter +
- *                  k*dt for k = 0 .. ceil((t_exit - t_enter)/dt) - 1. */
+ *                  k*dt for k = 0 .. ceil((t_exit - t_enter)/dt) - 1.
+ *  star_n, star_c0, star_off, star_w
+ *                  in-ray 3-axis Gaussian of Section 4.2 (Alg. 9-tap smoothing), the
+ *                  alternative to box_arm: each sample value v at point p becomes, for the
+ *                  axes e = x, then y, then z, v <- c0 v + sum_{k < star_n} w_k (cube[p +
+ *                  off_k e] + cube[p - off_k e]), every lookup a trilinear fetch of the raw
+ *                  cube (1 + 6 star_n fetches per sample; the paper's 9-tap form has star_n
+ *                  = 2, off = (1.3846153846, 3.2307692308), w = (0.3162162162, 0.0702702703),
+ *                  c0 = 0.2270270270).  star_n = 0 (up to SVR_MAX_STAR) disables it; offsets
+ *                  in voxels, finite, in [0, 64]; needs box_arm 0 and ratio 0. */
 typedef struct {
     int32_t mode;
     int32_t filter;
@@ -148,6 +159,10 @@ typedef struct {
     float min_t, max_t;
     float min_t2, max_t2;
     float ratio_lo, ratio_hi;
+    int32_t star_n;
+    float star_c0;
+    float star_off[SVR_MAX_STAR];
+    float star_w[SVR_MAX_STAR];
 } svr_params;
 
 /* Host-only check of a parameter set (everything that does not depend on a volume):

@@ -87,7 +87,8 @@ def camera_struct(cam):
 PARAM_DEFAULTS = dict(mode="mip0", filter="none", box_arm=0, mip_alpha=0, ratio=0,
                       opacity_from_lut=0, k=0.22, min_val=1e-6, ert=0.99, clim_lo=0.0,
                       clim_hi=0.0, dt=0.5, min_t=-math.inf, max_t=math.inf,
-                      min_t2=-math.inf, max_t2=math.inf, ratio_lo=0.0, ratio_hi=1.0)
+                      min_t2=-math.inf, max_t2=math.inf, ratio_lo=0.0, ratio_hi=1.0,
+                      star=None)
 
 
 def params_struct(params=None, **kw):
@@ -106,6 +107,16 @@ def params_struct(params=None, **kw):
     for name in ("k", "min_val", "ert", "clim_lo", "clim_hi", "dt", "min_t", "max_t",
                  "min_t2", "max_t2", "ratio_lo", "ratio_hi"):
         setattr(p, name, float(q[name]))
+    # in-ray Gaussian (Section 4.2): star = (c0, [(off_1, w_1), ...]) or None
+    if q["star"]:
+        c0, pairs = q["star"]
+        if len(pairs) > 4:
+            raise ValueError("at most 4 (offset, weight) pairs")
+        p.star_n = len(pairs)
+        p.star_c0 = float(c0)
+        for i, (o, w) in enumerate(pairs):
+            p.star_off[i] = float(o)
+            p.star_w[i] = float(w)
     return p
 
 

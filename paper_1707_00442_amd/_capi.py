@@ -50,7 +50,9 @@ class Params(C.Structure):
                 ("k", C.c_float), ("min_val", C.c_float), ("ert", C.c_float),
                 ("clim_lo", C.c_float), ("clim_hi", C.c_float), ("dt", C.c_float),
                 ("min_t", C.c_float), ("max_t", C.c_float), ("min_t2", C.c_float),
-                ("max_t2", C.c_float), ("ratio_lo", C.c_float), ("ratio_hi", C.c_float)]
+                ("max_t2", C.c_float), ("ratio_lo", C.c_float), ("ratio_hi", C.c_float),
+                ("star_n", C.c_int32), ("star_c0", C.c_float), ("star_off", C.c_float * 4),
+                ("star_w", C.c_float * 4)]
 
 
 _lib = None

@@ -106,6 +106,16 @@ svr_status check_params(const svr_params* p, const svr_volume* v) {
     if (p->filter == SVR_FILTER_SCALE)
         SVR_CHECK(isfinite(p->min_t) && isfinite(p->max_t) && p->min_t < p->max_t,
                   "domain scaling needs finite min_t < max_t");
+    SVR_CHECK(p->star_n >= 0 && p->star_n <= SVR_MAX_STAR, "star_n %d", p->star_n);
+    if (p->star_n > 0) {
+        SVR_CHECK(p->box_arm == 0 && p->ratio == 0,
+                  "the in-ray Gaussian (star_n > 0) takes box_arm 0 and ratio 0");
+        SVR_CHECK(isfinite(p->star_c0), "star_c0 must be finite");
+        for (int k = 0; k < p->star_n; ++k)
+            SVR_CHECK(isfinite(p->star_w[k]) && isfinite(p->star_off[k]) &&
+                          p->star_off[k] >= 0.0f && p->star_off[k] <= 64.0f,
+                      "star pair %d: offset in [0, 64] and finite weight", k);
+    }
     if (p->ratio) {
         SVR_CHECK(p->mode == SVR_MIP0, "line-ratio methods use mode SVR_MIP0");
         SVR_CHECK(p->box_arm == 0, "line-ratio methods take no box smoothing");

@@ -272,6 +272,11 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
     svr_status st = check_lut(lut);
     if (st) return st;
     if ((st = check_params(params, vols[0]))) return st;
+    if (params->star_n != 0) {
+        set_error("svr_batch_create: the in-ray Gaussian (star_n > 0) is not available in "
+                  "batched launches");
+        return SVR_EINVAL;
+    }
     if (params->ratio != 0) {
         set_error("svr_batch_create: line-ratio methods are not batched");
         return SVR_EINVAL;

@@ -61,13 +61,21 @@ struct BoxRing {
     }
 };
 
+// Smoothing of a sample before filter() (Alg. 1): none, the box mean along the ray
+// (Section 4.1) or the in-ray 3-axis Gaussian (Section 4.2).
+enum { kSmoothNone = 0, kSmoothBox = 1, kSmoothStar = 2 };
+
 // Run alive = per_sample(k, value, active) over the ray's samples k = 0 .. N-1, the value
-// being the raw sample or its box mean.
-template <bool BOX, class S, class Fn>
+// being the raw sample, its box mean or its in-ray Gaussian.
+template <int SMOOTH, class S, class Fn>
 __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, int arm, float* ring,
-                                               Fn&& per_sample) {
-    if (!BOX) {
+                                               const svr_params& st, Fn&& per_sample) {
+    if (SMOOTH == kSmoothNone) {
         drive(RaySource<S>(smp, r, 0.0f), r.n, per_sample);
+        return;
+    }
+    if (SMOOTH == kSmoothStar) {
+        drive(StarSource<S>(smp, st, r), r.n, per_sample);
         return;
     }
     BoxRing box(ring, arm);
@@ -81,16 +89,17 @@ __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, in
 }
 
 // The sample stream of one ray through the bricked volume: feed.run(body) delivers
-// alive = body(k, value, active) for k = 0 .. N-1 (raw samples or their box means).
-template <bool BOX, class Smp>
+// alive = body(k, value, active) for k = 0 .. N-1 (raw or smoothed samples).
+template <int SMOOTH, class Smp>
 struct GatherFeed {
     const Smp& smp;
     const RaySeg& r;
     int arm;
     float* ring;
+    const svr_params& st;
     template <class Fn>
     __device__ __forceinline__ void run(Fn&& body) const {
-        for_each_value<BOX>(smp, r, arm, ring, body);
+        for_each_value<SMOOTH>(smp, r, arm, ring, st, body);
     }
 };
 
@@ -99,7 +108,7 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
                                          const RaySeg& r, const Filt& F, Feed& feed,
                                          float4& res, int& count);
 
-template <int MODE, int RATIO, int DT, int C, bool WIDE, bool BOX, bool REUSE>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
@@ -111,7 +120,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     count = N;
 
     if (RATIO == 0) {
-        GatherFeed<BOX, Smp> feed{smp, r, a.p.box_arm, ring};
+        GatherFeed<SMOOTH, Smp> feed{smp, r, a.p.box_arm, ring, a.p};
         march_tf<MODE>(a, s_lut, r, F, feed, res, count);
         return;
     }
@@ -278,17 +287,21 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 
 // One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
 // is uniform); lanes outside the image pass inside = false and march no samples.  REUSE:
-// same-cell corner reuse (float32 storage at steps below a voxel).
-template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32>
+// same-cell corner reuse (float32 storage at steps below a voxel).  STAR: the in-ray
+// Gaussian, compiled into kernels of its own so the others do not carry its registers.
+template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32,
+          bool STAR = false>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
     const Filt F = make_filter(a);
     const RaySeg r = pixel_ray(a, px, py, inside);
-    if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, WIDE, true, REUSE>(a, s_lut, ring, r, F, res, count);
+    if (STAR)
+        march<MODE, 0, DT, C, WIDE, kSmoothStar, false>(a, s_lut, ring, r, F, res, count);
+    else if (RATIO == 0 && a.p.box_arm > 0)
+        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE>(a, s_lut, ring, r, F, res, count);
     else
-        march<MODE, RATIO, DT, C, WIDE, false, REUSE>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE>(a, s_lut, ring, r, F, res, count);
 }
 
 // Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works

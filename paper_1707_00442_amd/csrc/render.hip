@@ -12,7 +12,7 @@
 
 namespace svr {
 
-template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE, bool STAR>
 __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     extern __shared__ float4 smem[];
     float4* s_lut = smem;
@@ -32,7 +32,8 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     float4 res;
     int count;
     float* ring = reinterpret_cast<float*>(smem + n_lut + 1) + threadIdx.x;
-    render_ray<MODE, RATIO, DT, C, WIDE, REUSE>(a, s_lut, ring, px, py, inside, res, count);
+    render_ray<MODE, RATIO, DT, C, WIDE, REUSE, STAR>(a, s_lut, ring, px, py, inside, res,
+                                                      count);
     if (inside) {
         const size_t pix = (size_t)py * a.cam.width + px;
         a.out[pix] = res;
@@ -44,20 +45,38 @@ using RenderFn = void (*)(RenderArgs);
 
 template <int DT, int C, bool WIDE, bool REUSE>
 static RenderFn pick(int mode, int ratio) {
-    if (ratio == 1) return render_kernel<SVR_MIP0, 1, DT, C, WIDE, REUSE>;
-    if (ratio == 2) return render_kernel<SVR_MIP0, 2, DT, C, WIDE, REUSE>;
+    if (ratio == 1) return render_kernel<SVR_MIP0, 1, DT, C, WIDE, REUSE, false>;
+    if (ratio == 2) return render_kernel<SVR_MIP0, 2, DT, C, WIDE, REUSE, false>;
     switch (mode) {
-        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C, WIDE, REUSE>;
-        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C, WIDE, REUSE>;
-        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C, WIDE, REUSE>;
-        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C, WIDE, REUSE>;
-        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C, WIDE, REUSE>;
-        default: return render_kernel<SVR_AVIPRGB, 0, DT, C, WIDE, REUSE>;
+        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C, WIDE, REUSE, false>;
+        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C, WIDE, REUSE, false>;
+        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C, WIDE, REUSE, false>;
+        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C, WIDE, REUSE, false>;
+        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C, WIDE, REUSE, false>;
+        default: return render_kernel<SVR_AVIPRGB, 0, DT, C, WIDE, REUSE, false>;
+    }
+}
+
+// In-ray Gaussian kernels (no ratio, no reuse: the stencil's fetches are not along the ray).
+template <int DT, int C, bool WIDE>
+static RenderFn pick_star(int mode) {
+    switch (mode) {
+        case SVR_MIP0: return render_kernel<SVR_MIP0, 0, DT, C, WIDE, false, true>;
+        case SVR_MIP1: return render_kernel<SVR_MIP1, 0, DT, C, WIDE, false, true>;
+        case SVR_MIPRGB: return render_kernel<SVR_MIPRGB, 0, DT, C, WIDE, false, true>;
+        case SVR_AVIP0: return render_kernel<SVR_AVIP0, 0, DT, C, WIDE, false, true>;
+        case SVR_AVIP1: return render_kernel<SVR_AVIP1, 0, DT, C, WIDE, false, true>;
+        default: return render_kernel<SVR_AVIPRGB, 0, DT, C, WIDE, false, true>;
     }
 }
 
 template <int C, bool WIDE>
-static RenderFn pick_dt(int dtype, bool reuse, int mode, int ratio) {
+static RenderFn pick_dt(int dtype, bool reuse, bool star, int mode, int ratio) {
+    if (star) {
+        if (dtype == SVR_F16) return pick_star<SVR_F16, C, WIDE>(mode);
+        if (dtype == SVR_BF16) return pick_star<SVR_BF16, C, WIDE>(mode);
+        return pick_star<SVR_F32, C, WIDE>(mode);
+    }
     if (dtype == SVR_F16) return pick<SVR_F16, C, WIDE, false>(mode, ratio);
     if (dtype == SVR_BF16) return pick<SVR_BF16, C, WIDE, false>(mode, ratio);
     return reuse ? pick<SVR_F32, C, WIDE, true>(mode, ratio)
@@ -66,13 +85,14 @@ static RenderFn pick_dt(int dtype, bool reuse, int mode, int ratio) {
 
 // Same-cell reuse (float32 storage) only where consecutive samples can share a cell: steps
 // below one voxel.
-static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int mode, int ratio) {
+static RenderFn pick_any(int dtype, int brick, bool wide, float dt, bool star, int mode,
+                         int ratio) {
     const bool reuse = dtype == SVR_F32 && dt < 1.0f;
     if (brick == 16)
-        return wide ? pick_dt<16, true>(dtype, reuse, mode, ratio)
-                    : pick_dt<16, false>(dtype, reuse, mode, ratio);
-    return wide ? pick_dt<8, true>(dtype, reuse, mode, ratio)
-                : pick_dt<8, false>(dtype, reuse, mode, ratio);
+        return wide ? pick_dt<16, true>(dtype, reuse, star, mode, ratio)
+                    : pick_dt<16, false>(dtype, reuse, star, mode, ratio);
+    return wide ? pick_dt<8, true>(dtype, reuse, star, mode, ratio)
+                : pick_dt<8, false>(dtype, reuse, star, mode, ratio);
 }
 
 size_t render_lds_bytes(int lut_n, int box_arm, int ratio) {
@@ -97,7 +117,7 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
     const int tiles_y = (cam.height + kTile - 1) / kTile;
     a.nblocks = a.tiles_x * tiles_y;
     const bool wide = wide_volume(v->d) || (v2 != nullptr && wide_volume(v2->d));
-    RenderFn fn = pick_any(v->d.dtype, v->d.brick, wide, p.dt, p.mode, p.ratio);
+    RenderFn fn = pick_any(v->d.dtype, v->d.brick, wide, p.dt, p.star_n > 0, p.mode, p.ratio);
     const size_t lds = render_lds_bytes(lut.n, p.box_arm, p.ratio);
     hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(kBlock), lds, stream, a);
     return hip_fail(hipGetLastError(), "render launch");

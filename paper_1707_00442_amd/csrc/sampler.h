@@ -172,6 +172,48 @@ struct RaySource {
     }
 };
 
+// The in-ray 3-axis Gaussian of Section 4.2 (Alg. 9-tap smoothing, applied to the data axes
+// in turn): a sample value v at point p becomes, for e = x, then y, then z,
+// v <- c0 v + sum_k w_k (cube[p + off_k e] + cube[p - off_k e]), every lookup a trilinear
+// fetch of the raw cube.  The six fetches of one offset pair are independent and issued
+// together; the value is complete when next() returns.  The taps are read from the launch
+// parameters (svr_params star_n, star_c0, star_off, star_w).
+template <class S>
+struct StarSource {
+    using Fetch = float;
+    const S& smp;
+    const svr_params& st;
+    double px, py, pz, dqx, dqy, dqz;
+    __device__ __forceinline__ StarSource(const S& s, const svr_params& t, const RaySeg& r)
+        : smp(s), st(t), px(r.q0[0]), py(r.q0[1]), pz(r.q0[2]), dqx(r.dq[0]), dqy(r.dq[1]),
+          dqz(r.dq[2]) {}
+    __device__ __forceinline__ float star(double x, double y, double z) const {
+        float v = smp(x, y, z);
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f;  // per-axis sums over the pairs, in order
+        for (int k = 0; k < st.star_n; ++k) {
+            const double o = (double)st.star_off[k];
+            const float w = st.star_w[k];
+            const float xp = smp(x + o, y, z), xm = smp(x - o, y, z);
+            const float yp = smp(x, y + o, z), ym = smp(x, y - o, z);
+            const float zp = smp(x, y, z + o), zm = smp(x, y, z - o);
+            sx = fmaf(xm, w, fmaf(xp, w, sx));
+            sy = fmaf(ym, w, fmaf(yp, w, sy));
+            sz = fmaf(zm, w, fmaf(zp, w, sz));
+        }
+        v = fmaf(v, st.star_c0, sx);
+        v = fmaf(v, st.star_c0, sy);
+        return fmaf(v, st.star_c0, sz);
+    }
+    __device__ __forceinline__ Fetch next() {
+        const float v = star(px, py, pz);
+        px += dqx;
+        py += dqy;
+        pz += dqz;
+        return v;
+    }
+    __device__ __forceinline__ float value(const Fetch& f) const { return f; }
+};
+
 // The same point sampled in two co-registered volumes (line ratios).
 template <class S>
 struct PairSource {

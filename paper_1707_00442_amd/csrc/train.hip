@@ -528,9 +528,9 @@ static svr_status train_checks(const svr_volume* vol, const svr_camera* cam,
     if (st) return st;
     if ((st = check_params(p, vol))) return st;
     if (p->mode != SVR_AVIP0 || p->filter != SVR_FILTER_NONE || p->box_arm != 0 ||
-        p->ratio != 0 || p->opacity_from_lut != 1) {
+        p->ratio != 0 || p->opacity_from_lut != 1 || p->star_n != 0) {
         set_error("differentiable render: mode SVR_AVIP0, filter none, box_arm 0, ratio 0, "
-                  "opacity_from_lut 1");
+                  "star_n 0, opacity_from_lut 1");
         return SVR_EINVAL;
     }
     return SVR_OK;

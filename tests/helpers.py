@@ -48,6 +48,9 @@ def rounded(params):
     for k in F32_KEYS:
         if k in q:
             q[k] = f32(q[k])
+    if q.get("star"):
+        c0, pairs = q["star"]
+        q["star"] = (f32(c0), [(f32(o), f32(w)) for o, w in pairs])
     return q
 
 

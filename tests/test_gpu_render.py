@@ -95,6 +95,64 @@ def test_all_modes_filters_box(svr, ragged, mode, filt, box):
     assert hit > 2000
 
 
+# the paper's 9-tap in-ray stencil (Alg. 9-tap smoothing), and the 5-tap binomial
+# [1, 4, 6, 4, 1]/16 as plain pairs at offsets 1 and 2 plus a zero-weight pair at 0.5
+STAR9 = (0.2270270270, [(1.3846153846, 0.3162162162), (3.2307692308, 0.0702702703)])
+STAR5_3PAIRS = (0.375, [(1.0, 0.25), (2.0, 0.0625), (0.5, 0.0)])
+
+
+@pytest.mark.parametrize("mode", ["mip0", "mip1", "avip0", "aviprgb"])
+@pytest.mark.parametrize("filt", ["none", "clip"])
+def test_star_gaussian_in_ray(svr, ragged, mode, filt):
+    """The in-ray 3-axis Gaussian of Section 4.2 (the 9-tap stencil along x, then y, then z,
+    each axis centred on the previous result) against the oracle's reading of it."""
+    cube, lo, hi, cam = ragged
+    print(f"[star] mode={mode} filter={filt}", flush=True)
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, k=0.31, filter=filt, star=STAR9)
+    if filt == "clip":
+        params.update(min_t=1.5, max_t=12.0)
+    got, ns = gpu_render(svr, _vol(svr, cube), cam, to_cuda(lut), params, lo, hi)
+    err, frag, _ = compare_render(oracle, got, ns, cube, cam, lut, params, lo, hi,
+                                  margins=margins(lo, hi, params), cond_tol=COND_TOL)
+    hit = int((ns > 0).sum())
+    print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
+    assert err <= TOL32
+    assert frag.sum() < 0.05 * hit and hit > 2000
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_star_gaussian_half_storage_and_three_pairs(svr, ragged, storage):
+    """16-bit storage against the oracle on the dequantised cube; three offset pairs, one of
+    them with zero weight (the stencil still fetches it)."""
+    cube, lo, hi, cam = ragged
+    deq = quant.dequantize(cube, storage)
+    lut = synth.lut_heat(256)
+    params = dict(mode="avip0", k=0.31, star=STAR5_3PAIRS)
+    got, ns = gpu_render(svr, _vol(svr, cube, storage), cam, to_cuda(lut), params, lo, hi)
+    err, frag, _ = compare_render(oracle, got, ns, deq, cam, lut, params, lo, hi,
+                                  margins=margins(lo, hi, params), cond_tol=COND_TOL)
+    print(f"[star {storage}] max err {err:.3e} fragile {frag.sum()}", flush=True)
+    assert err <= TOL32
+
+
+def test_star_gaussian_rejected_combinations(svr, ragged):
+    """The in-ray Gaussian excludes box smoothing, the ratio methods, the differentiable
+    render and batched launches (host-side checks, before any launch)."""
+    cube, lo, hi, cam = ragged
+    vol = _vol(svr, cube)
+    lut = to_cuda(synth.lut_heat(256))
+    with pytest.raises(svr.SvrError):
+        svr.svr_render(vol, cam, lut, mode="mip0", box_arm=1, star=STAR9)
+    with pytest.raises(svr.SvrError):
+        svr.svr_render(vol, cam, lut, mode="mip0", ratio=1, star=STAR9, vol2=vol)
+    with pytest.raises(svr.SvrError):
+        svr.svr_render_train(vol, cam, to_cuda(synth.tf_ramp(64)),
+                             dict(mode="avip0", opacity_from_lut=1, star=STAR9))
+    with pytest.raises(svr.SvrError):
+        svr.svr_render(vol, cam, lut, mode="mip0", star=(0.2, [(70.0, 0.4)]))
+
+
 @pytest.mark.parametrize("mode", ["mip0", "avip0"])
 @pytest.mark.parametrize("box", [0, 5])
 def test_frame_rate_protocol_configuration(svr, mode, box):
