@@ -318,9 +318,10 @@ def run_protocol(torch, svr, synth, sizes=(128, 256, 512, 1024), canvas=1000, re
     """The paper's frame-rate benchmark (Section 6, Appendix B) on this GPU: uniform [0, 1)
     float32 cubes, one sample per voxel (dt = 1), the rotation views (10 degree steps), each
     frame timed on its own; fps = 1000 / median frame time over `reps` full rotations.
-    Kernels: raw and box smoothing of 3..11 samples (filterArm 1..5); MIP0, and AVIP0 with
-    k = 0.22 and clipping at minThreshold = 0.9 (the paper's settings).  Canvas sweep: MIP0 raw
-    at 500^2 .. 2000^2."""
+    Kernels: raw, box smoothing of 3..11 samples (filterArm 1..5) and the in-ray N-tap
+    Gaussians (N = 5, 9, 13); MIP0, and AVIP0 with k = 0.22 and clipping at minThreshold = 0.9
+    (the paper's settings).  Canvas sweep: MIP0 raw at 500^2 .. 2000^2."""
+    from paper_1707_00442_amd import taps as tapgen
     lut = torch.from_numpy(synth.lut_heat(256)).cuda()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -344,14 +345,16 @@ def run_protocol(torch, svr, synth, sizes=(128, 256, 512, 1024), canvas=1000, re
         del cube
         views = [v.as_f32() for v in synth.rotation_views(n, n, n, canvas, canvas)]
         out = torch.empty((canvas, canvas, 4), dtype=torch.float32, device="cuda")
+        kernels = [("raw", {})] + [(f"box{2 * a + 1}", dict(box_arm=a)) for a in range(1, 6)]
+        kernels += [(f"gauss{N}", dict(star=tapgen.star(N))) for N in (5, 9, 13)]
         for mode in ("mip0", "avip0"):
-            for arm in range(6):
-                p = dict(mode=mode, k=0.22, dt=1.0, box_arm=arm, clim_lo=lo, clim_hi=hi)
+            for name, extra in kernels:
+                p = dict(mode=mode, k=0.22, dt=1.0, clim_lo=lo, clim_hi=hi, **extra)
                 if mode == "avip0":
                     p.update(filter="clip", min_t=0.9)
                 svr.svr_render(vol, views[0], lut, p, out=out)
-                name = "raw" if arm == 0 else f"box{2 * arm + 1}"
                 res["fps"][f"{n}^3 {mode} {name}"] = round(median_fps(vol, views, p, out), 1)
+                log(f"protocol: {n}^3 {mode} {name}: {res['fps'][f'{n}^3 {mode} {name}']} fps")
         for cv in (500, 1000, 1500, 2000):
             cviews = [v.as_f32() for v in synth.rotation_views(n, n, n, cv, cv)]
             cout = torch.empty((cv, cv, 4), dtype=torch.float32, device="cuda")

@@ -7,6 +7,11 @@
 * paper9(): the discrete 9-tap kernel behind the paper's linear-sampling 9-tap shader
   (centre weight 0.2270270270; fetches at +-1.3846153846 and +-3.2307692308 weighted
   0.3162162162 and 0.0702702703, each fetch blending its two neighbouring voxels).
+* star(N): the in-ray stencil of the N-tap Gaussian (N = 5, 9, 13) in linear-sampling form,
+  (c0, [(offset, weight), ...]) for svr_params star_*: binomial row N + 3 with its two
+  outermost taps dropped on each side and renormalised, then neighbouring taps paired into one
+  fetch each (weight w_a + w_b at offset (a w_a + b w_b) / (w_a + w_b)).  N = 9 reproduces the
+  paper's printed constants; 3 (N - 1)/2 + 1 fetches per sample, the paper's count.
 """
 from __future__ import annotations
 
@@ -40,3 +45,18 @@ def paper9():
             taps[4 + side * i] += wt * (1.0 - f)
             taps[4 + side * (i + 1)] += wt * f
     return taps.astype(np.float32)
+
+
+def star(N):
+    if N not in (5, 9, 13):
+        raise ValueError("N-tap in-ray Gaussian for N = 5, 9 or 13")
+    n = N + 3
+    row = np.array([math.comb(n, j) for j in range(n + 1)], dtype=np.float64)[2:-2]
+    row /= row.sum()
+    r = N // 2
+    c0 = row[r]
+    pairs = []
+    for a in range(1, r + 1, 2):
+        wa, wb = row[r + a], row[r + a + 1]
+        pairs.append(((a * wa + (a + 1) * wb) / (wa + wb), wa + wb))
+    return float(c0), [(float(o), float(w)) for o, w in pairs]
