@@ -150,8 +150,8 @@ def load_traffic(kernel):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (the multi-GPU split is described in DESIGN.md, not built)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the split over several GPUs is a design, not implemented)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -167,7 +167,7 @@ def main():
     nx, ny, nz = 512, 512, 1024
     W, H = 1920, 1080
     log("building the 512x512x1024 cube")
-    cube_np = synth.cfg1_cube(0)
+    cube_np = synth.hi_cube_512x512x1024(0)
     cube = torch.from_numpy(cube_np).cuda()
     lo, hi = svr.svr_minmax(cube)
     views = [v.as_f32() for v in synth.rotation_views(nx, ny, nz, W, H)]
@@ -404,7 +404,7 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
         fn = lambda: svr.svr_moments(cube, out=mom)  # noqa: E731
     elif name in ("train_fwd", "train_bwd"):
         # the differentiable form: 256^3 cube, 1024x1024, 64-point transfer function
-        c4 = torch.from_numpy(synth.cfg4_cube(0)).cuda()
+        c4 = torch.from_numpy(synth.disc_cube_256(0)).cuda()
         l4, h4 = svr.svr_minmax(c4)
         v4 = svr.svr_volume_create(c4)
         tf = torch.from_numpy(synth.tf_ramp(64)).cuda()
@@ -506,7 +506,7 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
     vol32.close()
     # differentiable forward + adjoint: 256^3 cube, 64-point transfer function
     log("form: forward + adjoint")
-    c4 = torch.from_numpy(synth.cfg4_cube(0)).cuda()
+    c4 = torch.from_numpy(synth.disc_cube_256(0)).cuda()
     l4, h4 = svr.svr_minmax(c4)
     v4 = svr.svr_volume_create(c4)
     tf = torch.from_numpy(synth.tf_ramp(64)).cuda()

@@ -101,17 +101,17 @@ def disc_cube(nx, ny, nz, ndiscs, seed, dv_chan=4.0, centre_margin=40.0, rd_rang
     return cube
 
 
-def cfg0_cube(seed=0):
+def blob_cube_64(seed=0):
     """64^3 float32: noise sigma 1 + 3 blobs whose centroid velocity shifts with x."""
     return blob_cube(64, 3, seed)
 
 
-def cfg1_cube(seed=0, nx=512, ny=512, nz=1024):
+def hi_cube_512x512x1024(seed=0, nx=512, ny=512, nz=1024):
     """512 x 512 x 1024 float32 HI-like cube with 50 discs (4 km/s channels)."""
     return disc_cube(nx, ny, nz, 50, seed)
 
 
-def cfg4_cube(seed=0, n=256, ndiscs=10):
+def disc_cube_256(seed=0, n=256, ndiscs=10):
     """256^3 float32: noise + 10 discs (the 512x512x1024 recipe scaled by 1/2 in space,
     8 km/s channels)."""
     s = n / 256.0

@@ -34,7 +34,7 @@ def svr():
 @pytest.fixture(scope="module")
 def full(svr):
     print("[full] building the 512x512x1024 cube", flush=True)
-    cube = synth.cfg1_cube(0)
+    cube = synth.hi_cube_512x512x1024(0)
     t = to_cuda(cube)
     lo, hi = svr.svr_minmax(t)
     rlo, rhi = quant.finite_minmax(cube)

@@ -95,7 +95,7 @@ def test_moments_strided_view(svr):
 def test_moments_full_size_sampled_spectra(svr):
     """512x512x1024 cube (the main workload), whole spectral axis, at the launch the
     benchmark times; 4000 spectra checked against the oracle one by one."""
-    cube = synth.cfg1_cube(0)
+    cube = synth.hi_cube_512x512x1024(0)
     m0, m1, am = svr.svr_moments(to_cuda(cube))
     svr.svr_sync()
     rng = np.random.default_rng(11)

@@ -30,14 +30,14 @@ def _vol(svr, cube, storage="f32", brick=8):
     return svr.svr_volume_create(to_cuda(cube), storage=storage, brick=brick)
 
 
-# ----------------------------------------------------------------------------- cfg0
+# ----------------------------------------------------------------------------- 64^3 blobs, parallel view
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("case", ["mip0", "avip0", "avip0_clip"])
-def test_cfg0_parity(svr, seed, case):
+def test_blob64_parallel_parity(svr, seed, case):
     """64^3 noise + 3 blobs, parallel projection along +z, 256x256, 128 samples per ray,
     256-entry ramp table: MIP0 and AVIP0 (k = 0.22; no filter and clip at minT = 3)."""
-    print(f"[cfg0] seed={seed} case={case}", flush=True)
-    cube = synth.cfg0_cube(seed)
+    print(f"[blob64] seed={seed} case={case}", flush=True)
+    cube = synth.blob_cube_64(seed)
     lo, hi = quant.finite_minmax(cube)
     cam = synth.ortho_axis(64, 64, 64, 256, 256, "+z").as_f32()
     lut = synth.lut_ramp(256)
@@ -225,11 +225,11 @@ def torch_equal(a, b):
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("mode", ["mip0", "avip0"])
-def test_half_storage_cfg0(svr, storage, seed, mode):
+def test_half_storage_blob64(svr, storage, seed, mode):
     """The 64^3 workload stored as FP16/BF16 (camera and ramp table as for float32): FP32
     arithmetic gives <= 1e-5 against the oracle on the stored (dequantised) values and
     <= 2e-3 against the oracle on the original float32 cube."""
-    cube = synth.cfg0_cube(seed)
+    cube = synth.blob_cube_64(seed)
     deq = quant.dequantize(cube, storage)
     lo, hi = quant.finite_minmax(deq)
     cam = synth.ortho_axis(64, 64, 64, 256, 256, "+z").as_f32()
@@ -267,7 +267,7 @@ def test_half_storage_cfg0(svr, storage, seed, mode):
 def test_half_storage_perspective(svr, storage, mode):
     """FP16/BF16 storage in perspective with every other transfer function: <= 1e-5
     against the oracle on the stored values."""
-    cube = synth.cfg0_cube(1)
+    cube = synth.blob_cube_64(1)
     deq = quant.dequantize(cube, storage)
     lo, hi = quant.finite_minmax(deq)
     cam = synth.perspective_lookat(64, 64, 64, 30.0, 25.0, 140.0, 40.0, 128, 96).as_f32()
@@ -283,7 +283,7 @@ def test_half_storage_perspective(svr, storage, mode):
 def test_fp16_exact_cube_renders_bitwise_equal(svr):
     """A cube whose values are exactly representable in binary16 renders identically from
     float16 and float32 storage (the arithmetic is float32 either way)."""
-    cube = quant.dequantize(synth.cfg0_cube(2), "f16")
+    cube = quant.dequantize(synth.blob_cube_64(2), "f16")
     cam = synth.perspective_lookat(64, 64, 64, 10.0, 30.0, 140.0, 40.0, 96, 64).as_f32()
     lut = to_cuda(synth.lut_heat(256))
     a = _vol(svr, cube, "f32")
@@ -435,7 +435,7 @@ def test_ratio_methods(svr, method, clip):
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 def test_line_ratio_pass(svr, dtype):
-    cube = synth.cfg0_cube(0)
+    cube = synth.blob_cube_64(0)
     if dtype == "f16":
         cube = quant.dequantize(cube, "f16")
     import torch

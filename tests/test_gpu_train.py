@@ -121,7 +121,7 @@ def test_gradients_ragged_image(svr):
 def test_gradients_full_size_sampled_rays(svr):
     """256^3 cube (noise + 10 discs), 1024x1024 image: upstream gradient on 1500 sampled
     pixels; the oracle differentiates those rays."""
-    cube = synth.cfg4_cube(0)
+    cube = synth.disc_cube_256(0)
     lo, hi = quant.finite_minmax(cube)
     cam = synth.perspective_lookat(256, 256, 256, 30.0, 20.0, 2 * 0.5 * 256 * 3 ** 0.5, 40.0,
                                    1024, 1024).as_f32()

@@ -86,7 +86,7 @@ def test_ray_box_entry_on_surface_and_chord_by_bruteforce():
 def test_mip0_axis_aligned_is_column_max(seed):
     """Eq. MIP along z with one ray per voxel column (64x64 image on a 64^3 cube): the
     result is colourMap(max_z V) exactly (trilinear weights are 0/1 or clamp)."""
-    cube = synth.cfg0_cube(seed)
+    cube = synth.blob_cube_64(seed)
     lo, hi = quant.finite_minmax(cube)
     cam = synth.ortho_axis(64, 64, 64, 64, 64, "+z")
     lut = synth.lut_heat(256)
@@ -101,7 +101,7 @@ def test_mip0_axis_aligned_is_column_max(seed):
 def test_mip0_oversampled_matches_library_trilinear_max():
     """256x256 rays over a 64^3 cube: MIP0 equals the max over library-interpolated samples
     at the closed-form sample positions z = -0.5 + 0.5 k, k = 0..127."""
-    cube = synth.cfg0_cube(0)
+    cube = synth.blob_cube_64(0)
     lo, hi = quant.finite_minmax(cube)
     cam = synth.ortho_axis(64, 64, 64, 256, 256, "+z")
     lut = synth.lut_ramp(256)
@@ -145,7 +145,7 @@ def test_mip1_and_rgb_use_last_argmax_and_loc():
 
 def test_mirror_views_give_mirrored_mip0():
     """Parallel views along +z and -z see the same maxima: the images are mirror images."""
-    cube = synth.cfg0_cube(1)
+    cube = synth.blob_cube_64(1)
     lo, hi = quant.finite_minmax(cube)
     lut = synth.lut_ramp(256)
     a = synth.ortho_axis(64, 64, 64, 128, 128, "+z")
@@ -333,7 +333,7 @@ def test_avip_gradient_matches_central_differences():
 def test_filters_reduce_to_identity_when_inactive():
     """Clipping with minT below and maxT above the data, domain scaling over [lo, hi],
     and box smoothing of a constant cube all leave the render unchanged."""
-    cube = synth.cfg0_cube(2)
+    cube = synth.blob_cube_64(2)
     lo, hi = quant.finite_minmax(cube)
     cam = synth.perspective_lookat(64, 64, 64, 20.0, 10.0, 120.0, 40.0, 48, 32)
     lut = synth.lut_heat(256)
@@ -399,7 +399,7 @@ def test_box_smoothing_is_mean_along_the_ray():
 
 # ------------------------------------------------------------------ misses (P14)
 def test_missing_rays_and_backward_camera_give_zero():
-    cube = synth.cfg0_cube(0)
+    cube = synth.blob_cube_64(0)
     lut = synth.lut_ramp(256)
     away = synth.Camera(1, (31.5, 31.5, -50.0), (0.2, 0, 0), (0, 0.2, 0), (0, 0, -1.0), 8, 8)
     r, _, ns = oracle.render(cube, away, lut, dict(mode="avip0", lo=-5, hi=20))
@@ -410,7 +410,7 @@ def test_missing_rays_and_backward_camera_give_zero():
 
 
 def test_eye_inside_volume_starts_at_eye():
-    cube = synth.cfg0_cube(0)
+    cube = synth.blob_cube_64(0)
     lut = synth.lut_ramp(256)
     cam = synth.Camera(1, (31.5, 31.5, 31.5), (0.3, 0, 0), (0, 0.3, 0), (0, 0, 1.0), 2, 2)
     _, _, ns = oracle.render(cube, cam, lut, dict(mode="mip0", lo=-5, hi=20, dt=0.5))
@@ -453,7 +453,7 @@ def test_ratio_render_methods_on_proportional_lines():
 
 
 def test_ratio_of_a_cube_with_itself_is_one():
-    cube = synth.cfg0_cube(0)
+    cube = synth.blob_cube_64(0)
     R = oracle.line_ratio(cube, 10, 10, 20, datamin=-99.0)
     pos = cube[10:30] > 0
     assert np.all(R[pos] == 1.0)
