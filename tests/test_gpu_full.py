@@ -244,3 +244,36 @@ def test_full_batched_sub_cubes(svr):
         b.close()
     for v in vols:
         v.close()
+
+
+def test_render_volume_beyond_4gib(svr):
+    """A 1024 x 1024 x 768 float32 cube bricks into 4.8 GB, so its renders take the 64-bit
+    addressing path (the other tests stay below 4 GiB and use 32-bit offsets); sampled
+    pixels of every transfer function against the oracle."""
+    import torch
+    nx, ny, nz = 1024, 1024, 768
+    cube = synth.smooth_analytic_cube(nx, ny, nz)
+    t = to_cuda(cube)
+    vol = svr.svr_volume_create(t)
+    info = svr.svr_volume_info(vol)
+    print(f"[wide] bricked volume {info['bytes'] / 2**30:.2f} GiB", flush=True)
+    assert info["bytes"] > 4 * 2**30
+    del t
+    torch.cuda.empty_cache()
+    lo, hi = quant.finite_minmax(cube)
+    cam = synth.rotation_views(nx, ny, nz, 960, 540)[4].as_f32()
+    lut_np = synth.lut_heat(256)
+    lut = to_cuda(lut_np)
+    for mode in MODES:
+        p = dict(mode=mode, k=0.1)
+        img, ns = svr.svr_render(vol, cam, lut, p, clim_lo=lo, clim_hi=hi, samples=True)
+        svr.svr_sync()
+        got = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        ns = ns.cpu().numpy().ravel()
+        pix = _sample_pixels(ns, 300, seed=3)
+        err, frag, _ = compare_render(oracle, got[pix], ns[pix], cube, cam, lut_np, p, lo, hi,
+                                      pixels=pix, margins=margins(lo, hi, p),
+                                      cond_tol=COND_TOL)
+        print(f"  [wide] {mode}: max err {err:.3e} fragile {frag.sum()}", flush=True)
+        assert err <= TOL32
+    vol.close()
