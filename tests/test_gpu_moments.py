@@ -135,3 +135,12 @@ def test_moments_argmax_matches_mip1_location(svr):
     assert robust.mean() > 0.9
     ref = (amax + 0.5) / nz
     assert np.max(np.abs(red - ref)[robust]) < 1e-5
+
+
+def test_moments_degenerate_shapes(svr):
+    """One voxel; one spectrum; one channel over a row wider than a workgroup."""
+    rng = np.random.default_rng(12)
+    for shape in ((1, 1, 1), (37, 1, 1), (1, 3, 300), (40, 2, 257)):
+        cube = rng.standard_normal(shape).astype(np.float32)
+        _check(svr, cube)
+        _check(svr, cube, dv=0.5, min_t=-0.5)

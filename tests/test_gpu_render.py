@@ -363,11 +363,11 @@ def test_edge_cases(svr):
     cam = synth.Camera(0, (0.0, 0.0, -3.0), (0.5, 0, 0), (0, 0.5, 0), (0, 0, 1.0), 1, 1)
     for mode in MODES:
         vol = _vol(svr, one)
-        got, ns = gpu_render(svr, vol, cam, lut, dict(mode=mode), 0.0, 1.0)
-        err, frag, _ = compare_render(oracle, got, ns, one, cam, lut_np, dict(mode=mode),
-                                      0.0, 1.0)
-        assert ns[0] == 2
-        assert err <= TOL32
+        for p in (dict(mode=mode), dict(mode=mode, star=STAR9)):  # stencil entirely clamped
+            got, ns = gpu_render(svr, vol, cam, lut, p, 0.0, 1.0)
+            err, frag, _ = compare_render(oracle, got, ns, one, cam, lut_np, p, 0.0, 1.0)
+            assert ns[0] == 2
+            assert err <= TOL32
     # one channel thick, camera facing away, eye inside, missing rays, huge step
     thin = synth.blob_cube(20, 2, seed=1)[:1].copy()
     lo, hi = quant.finite_minmax(thin)
@@ -380,7 +380,8 @@ def test_edge_cases(svr):
     vol = _vol(svr, thin)
     for cam in cams:
         cam = cam.as_f32()
-        for p in (dict(mode="mip1"), dict(mode="avip0", dt=7.0), dict(mode="aviprgb")):
+        for p in (dict(mode="mip1"), dict(mode="avip0", dt=7.0), dict(mode="aviprgb"),
+                  dict(mode="avip0", star=STAR9)):
             got, ns = gpu_render(svr, vol, cam, lut, p, lo, hi)
             err, frag, _ = compare_render(oracle, got, ns, thin, cam, lut_np, p, lo, hi,
                                           margins=margins(lo, hi, p))
