@@ -67,20 +67,20 @@ enum { kSmoothNone = 0, kSmoothBox = 1, kSmoothStar = 2 };
 
 // Run alive = per_sample(k, value, active) over the ray's samples k = 0 .. N-1, the value
 // being the raw sample, its box mean or its in-ray Gaussian.
-template <int SMOOTH, class S, class Fn>
+template <int SMOOTH, int NS, class S, class Fn>
 __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, int arm, float* ring,
                                                const svr_params& st, Fn&& per_sample) {
     if (SMOOTH == kSmoothNone) {
-        drive(RaySource<S>(smp, r, 0.0f), r.n, per_sample);
+        drive<NS>(RaySource<S>(smp, r, 0.0f), r.n, per_sample);
         return;
     }
-    if (SMOOTH == kSmoothStar) {
-        drive(StarSource<S>(smp, st, r), r.n, per_sample);
+    if (SMOOTH == kSmoothStar) {  // values complete at fetch time: one ahead is enough
+        drive<2>(StarSource<S>(smp, st, r), r.n, per_sample);
         return;
     }
     BoxRing box(ring, arm);
     const int lead = 2 * arm;
-    drive(RaySource<S>(smp, r, (float)(-arm)), r.n > 0 ? r.n + lead : 0,
+    drive<NS>(RaySource<S>(smp, r, (float)(-arm)), r.n > 0 ? r.n + lead : 0,
           [&](int j, float raw, bool active) -> bool {
               float mean;
               if (!box.push(j, raw, mean)) return active;  // still filling the window
@@ -90,7 +90,7 @@ __device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, in
 
 // The sample stream of one ray through the bricked volume: feed.run(body) delivers
 // alive = body(k, value, active) for k = 0 .. N-1 (raw or smoothed samples).
-template <int SMOOTH, class Smp>
+template <int SMOOTH, int NS, class Smp>
 struct GatherFeed {
     const Smp& smp;
     const RaySeg& r;
@@ -99,7 +99,7 @@ struct GatherFeed {
     const svr_params& st;
     template <class Fn>
     __device__ __forceinline__ void run(Fn&& body) const {
-        for_each_value<SMOOTH>(smp, r, arm, ring, st, body);
+        for_each_value<SMOOTH, NS>(smp, r, arm, ring, st, body);
     }
 };
 
@@ -120,7 +120,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     count = N;
 
     if (RATIO == 0) {
-        GatherFeed<SMOOTH, Smp> feed{smp, r, a.p.box_arm, ring, a.p};
+        GatherFeed<SMOOTH, drive_slots<MODE, DT>(), Smp> feed{smp, r, a.p.box_arm, ring, a.p};
         march_tf<MODE>(a, s_lut, r, F, feed, res, count);
         return;
     }
@@ -132,7 +132,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
         const bool clip = a.p.filter == SVR_FILTER_CLIP;
         const float rinv = a.p.ratio_hi > a.p.ratio_lo ? 1.0f / (a.p.ratio_hi - a.p.ratio_lo) : 0.0f;
         float m1 = -INFINITY, m2 = -INFINITY, smax = -INFINITY;
-        drive(PairSource<Smp>(smp, smp2, r), N, [&](int, float2 v, bool active) -> bool {
+        drive<3>(PairSource<Smp>(smp, smp2, r), N, [&](int, float2 v, bool active) -> bool {
             float v1 = v.x, v2 = v.y;
             if (clip) {
                 v1 = (v1 < a.p.min_t || v1 > a.p.max_t) ? F.lo : v1;
