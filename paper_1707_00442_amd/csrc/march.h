@@ -108,7 +108,7 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
                                          const RaySeg& r, const Filt& F, Feed& feed,
                                          float4& res, int& count);
 
-template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE, int NS>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
@@ -120,7 +120,7 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     count = N;
 
     if (RATIO == 0) {
-        GatherFeed<SMOOTH, drive_slots<MODE, DT>(), Smp> feed{smp, r, a.p.box_arm, ring, a.p};
+        GatherFeed<SMOOTH, NS, Smp> feed{smp, r, a.p.box_arm, ring, a.p};
         march_tf<MODE>(a, s_lut, r, F, feed, res, count);
         return;
     }
@@ -288,20 +288,21 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 // One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
 // is uniform); lanes outside the image pass inside = false and march no samples.  REUSE:
 // same-cell corner reuse (float32 storage at steps below a voxel).  STAR: the in-ray
-// Gaussian, compiled into kernels of its own so the others do not carry its registers.
+// Gaussian, compiled into kernels of its own so the others do not carry its registers.  NS:
+// fetch slots of the sample loop.
 template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32,
-          bool STAR = false>
+          bool STAR = false, int NS = drive_slots<MODE, DT>()>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
     const Filt F = make_filter(a);
     const RaySeg r = pixel_ray(a, px, py, inside);
     if (STAR)
-        march<MODE, 0, DT, C, WIDE, kSmoothStar, false>(a, s_lut, ring, r, F, res, count);
+        march<MODE, 0, DT, C, WIDE, kSmoothStar, false, NS>(a, s_lut, ring, r, F, res, count);
     else if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE, NS>(a, s_lut, ring, r, F, res, count);
     else
-        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE, NS>(a, s_lut, ring, r, F, res, count);
 }
 
 // Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works
