@@ -108,11 +108,12 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
                                          const RaySeg& r, const Filt& F, Feed& feed,
                                          float4& res, int& count);
 
-template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE, int NS>
+template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE, int NS,
+          bool PACK>
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
-    using Smp = Sampler<DT, C, WIDE, REUSE>;
+    using Smp = Sampler<DT, C, WIDE, REUSE, PACK>;
     const Smp smp(a.v);
     const int N = r.n;
     const float n_lut = (float)(a.lut_n - 1);
@@ -289,20 +290,20 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 // is uniform); lanes outside the image pass inside = false and march no samples.  REUSE:
 // same-cell corner reuse (float32 storage at steps below a voxel).  STAR: the in-ray
 // Gaussian, compiled into kernels of its own so the others do not carry its registers.  NS:
-// fetch slots of the sample loop.
+// fetch slots of the sample loop.  PACK: 16-bit corners stay packed while in flight.
 template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32,
-          bool STAR = false, int NS = drive_slots<MODE, DT>()>
+          bool STAR = false, int NS = drive_slots<MODE, DT>(), bool PACK = true>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
     const Filt F = make_filter(a);
     const RaySeg r = pixel_ray(a, px, py, inside);
     if (STAR)
-        march<MODE, 0, DT, C, WIDE, kSmoothStar, false, NS>(a, s_lut, ring, r, F, res, count);
+        march<MODE, 0, DT, C, WIDE, kSmoothStar, false, NS, PACK>(a, s_lut, ring, r, F, res, count);
     else if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE, NS>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
     else
-        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE, NS>(a, s_lut, ring, r, F, res, count);
+        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
 }
 
 // Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works

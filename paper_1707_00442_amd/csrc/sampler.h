@@ -16,8 +16,9 @@ namespace svr {
 //
 // WIDE = false addresses the storage with 32-bit byte offsets from a scalar base (volumes
 // below 4 GiB); WIDE = true forms 64-bit addresses.  REUSE enables the same-cell reuse of
-// RaySource (float32 storage only).
-template <int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32>
+// RaySource (float32 storage only).  PACK keeps 16-bit corners packed while their loads are
+// in flight (see Fetch).
+template <int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32, bool PACK = true>
 struct Sampler {
     using T = typename Elem<DT>::T;
     static constexpr int E = C + 1;
@@ -27,17 +28,27 @@ struct Sampler {
     // a voxel; with two loads per sample (16-bit storage), or at steps where every sample
     // changes cell, its selects and registers cost more than it saves.
     static constexpr bool kReuse = REUSE && DT == SVR_F32;
+    static constexpr bool kPack = PACK && DT != SVR_F32;
     const T* data;
     double xm, ym, zm;
     uint32_t nbx, nby, pitch;
 
     // Loads in flight for one sample: its eight corners and the cell fractions; reuse marks
     // a sample in the same cell as the one fetched before it (no loads issued, corners 0).
-    struct Fetch {
+    // Packed 16-bit fetches keep the four loaded words (two corners each) and convert them
+    // only when the sample is blended, so a fetch slot holds half the registers while in
+    // flight; that lets the render kernels keep more samples in flight at the same occupancy.
+    struct FetchF32 {
         float c000, c100, c010, c110, c001, c101, c011, c111;
         float fx, fy, fz;
         bool reuse;
     };
+    struct FetchPacked {
+        uint32_t w0, w1, w2, w3;  // (c000, c010), (c100, c110), (c001, c011), (c101, c111)
+        float fx, fy, fz;
+        bool reuse;
+    };
+    using Fetch = typename std::conditional<kPack, FetchPacked, FetchF32>::type;
 
     // Brick counts and the pitch are below 2^24 (checked at volume creation); the masks
     // let the compiler use 24-bit multiplies.
@@ -87,9 +98,11 @@ struct Sampler {
         const uint32_t o = offset((uint32_t)x, (uint32_t)y, (uint32_t)z);
         f.reuse = kReuse && o == last;
         last = o;
-        if (f.reuse) {
-            f.c000 = f.c100 = f.c010 = f.c110 = f.c001 = f.c101 = f.c011 = f.c111 = 0.0f;
-            return f;
+        if constexpr (!kPack) {
+            if (f.reuse) {
+                f.c000 = f.c100 = f.c010 = f.c110 = f.c001 = f.c101 = f.c011 = f.c111 = 0.0f;
+                return f;
+            }
         }
         const T* q = at(o);
         if constexpr (DT == SVR_F32) {
@@ -101,7 +114,7 @@ struct Sampler {
             f.c101 = Elem<DT>::get(q, E * E + 1);
             f.c011 = Elem<DT>::get(q, E * E + E);
             f.c111 = Elem<DT>::get(q, E * E + E + 1);
-        } else {
+        } else if constexpr (!kPack) {
             constexpr uint32_t kZ = 2 * C * E;  // next pair layer
             f.c000 = Elem<DT>::get(q, 0);
             f.c010 = Elem<DT>::get(q, 1);
@@ -111,15 +124,37 @@ struct Sampler {
             f.c011 = Elem<DT>::get(q, kZ + 1);
             f.c101 = Elem<DT>::get(q, kZ + 2);
             f.c111 = Elem<DT>::get(q, kZ + 3);
+        } else {
+            // pair elements start at even element offsets, so each pair is one aligned word
+            constexpr uint32_t kZw = C * E;  // next pair layer, in 32-bit words
+            const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+            f.w0 = qw[0];
+            f.w1 = qw[1];
+            f.w2 = qw[kZw];
+            f.w3 = qw[kZw + 1];
         }
         return f;
     }
 
+    // element h (0 = low, 1 = high half) of a word of two 16-bit elements, as float
+    static __device__ __forceinline__ float half(uint32_t w, int h) {
+        if constexpr (DT == SVR_BF16) return __uint_as_float(h ? (w & 0xffff0000u) : (w << 16));
+        else return (float)__builtin_bit_cast(_Float16, (uint16_t)(h ? (w >> 16) : w));
+    }
+
     static __device__ __forceinline__ float blend(const Fetch& f) {
-        const float a00 = fmaf(f.fx, f.c100 - f.c000, f.c000);
-        const float a10 = fmaf(f.fx, f.c110 - f.c010, f.c010);
-        const float a01 = fmaf(f.fx, f.c101 - f.c001, f.c001);
-        const float a11 = fmaf(f.fx, f.c111 - f.c011, f.c011);
+        float c000, c100, c010, c110, c001, c101, c011, c111;
+        if constexpr (!kPack) {
+            c000 = f.c000; c100 = f.c100; c010 = f.c010; c110 = f.c110;
+            c001 = f.c001; c101 = f.c101; c011 = f.c011; c111 = f.c111;
+        } else {
+            c000 = half(f.w0, 0); c010 = half(f.w0, 1); c100 = half(f.w1, 0); c110 = half(f.w1, 1);
+            c001 = half(f.w2, 0); c011 = half(f.w2, 1); c101 = half(f.w3, 0); c111 = half(f.w3, 1);
+        }
+        const float a00 = fmaf(f.fx, c100 - c000, c000);
+        const float a10 = fmaf(f.fx, c110 - c010, c010);
+        const float a01 = fmaf(f.fx, c101 - c001, c001);
+        const float a11 = fmaf(f.fx, c111 - c011, c011);
         const float b0 = fmaf(f.fy, a10 - a00, a00);
         const float b1 = fmaf(f.fy, a11 - a01, a01);
         return fmaf(f.fz, b1 - b0, b0);
@@ -155,20 +190,23 @@ struct RaySource {
         return f;
     }
     __device__ __forceinline__ float value(const Fetch& f) {
-        if constexpr (!S::kReuse) return S::blend(f);
-        const bool r = f.reuse;
-        lc.c000 = r ? lc.c000 : f.c000;
-        lc.c100 = r ? lc.c100 : f.c100;
-        lc.c010 = r ? lc.c010 : f.c010;
-        lc.c110 = r ? lc.c110 : f.c110;
-        lc.c001 = r ? lc.c001 : f.c001;
-        lc.c101 = r ? lc.c101 : f.c101;
-        lc.c011 = r ? lc.c011 : f.c011;
-        lc.c111 = r ? lc.c111 : f.c111;
-        lc.fx = f.fx;
-        lc.fy = f.fy;
-        lc.fz = f.fz;
-        return S::blend(lc);
+        if constexpr (!S::kReuse) {
+            return S::blend(f);
+        } else {
+            const bool r = f.reuse;
+            lc.c000 = r ? lc.c000 : f.c000;
+            lc.c100 = r ? lc.c100 : f.c100;
+            lc.c010 = r ? lc.c010 : f.c010;
+            lc.c110 = r ? lc.c110 : f.c110;
+            lc.c001 = r ? lc.c001 : f.c001;
+            lc.c101 = r ? lc.c101 : f.c101;
+            lc.c011 = r ? lc.c011 : f.c011;
+            lc.c111 = r ? lc.c111 : f.c111;
+            lc.fx = f.fx;
+            lc.fy = f.fy;
+            lc.fz = f.fz;
+            return S::blend(lc);
+        }
     }
 };
 
@@ -258,13 +296,14 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
 
 // Fetch slots of the sample loop per transfer function and storage type (measured on the
 // 512 x 512 x 1024 rotation views: deeper pipelines keep more loads in flight per wave but
-// need more registers, so the best depth depends on the per-sample state each mode keeps).
+// need more registers, so the best depth depends on the per-sample state each mode keeps;
+// packed 16-bit slots are half the size of float32 ones and go deeper).
 template <int MODE, int DT>
 constexpr int drive_slots() {
-    if (MODE == SVR_MIP0 || MODE == SVR_MIP1 || MODE == SVR_MIPRGB) return 6;
-    if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 4 : 6;
-    if (MODE == SVR_AVIP0) return DT == SVR_F32 ? 6 : 4;
-    return 6;  // SVR_AVIP1
+    if (MODE == SVR_MIP0 || MODE == SVR_MIP1 || MODE == SVR_MIPRGB) return DT == SVR_F32 ? 6 : 8;
+    if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 4 : 7;
+    if (MODE == SVR_AVIP0) return 6;
+    return DT == SVR_F32 ? 6 : 8;  // SVR_AVIP1
 }
 
 }  // namespace svr
