@@ -39,7 +39,7 @@ def _subcubes(count, seed, scale=0.25):
     return out
 
 
-@pytest.mark.parametrize("mode", ["mip0", "avip0", "mip1", "aviprgb"])
+@pytest.mark.parametrize("mode", ["mip0", "mip1", "miprgb", "avip0", "avip1", "aviprgb"])
 @pytest.mark.parametrize("tune", [False, True])
 def test_batched_equals_single_renders(svr, mode, tune):
     import torch
