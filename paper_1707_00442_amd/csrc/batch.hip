@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchArgs b) {
             a.nblocks = 0;
             float4 res;
             int count;
-            render_ray<MODE, 0, DT, C, WIDE, DT == SVR_F32, false, batch_slots<MODE>(), false>(
+            render_ray<MODE, 0, DT, C, WIDE, DT == SVR_F32, kSmoothAuto, batch_slots<MODE>(), false>(
                 a, s_lut, ring, px, py, inside, res, count);
             if (inside) bv.out[(size_t)py * bv.cam.width + px] = res;
         }

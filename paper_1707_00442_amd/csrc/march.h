@@ -62,8 +62,9 @@ struct BoxRing {
 };
 
 // Smoothing of a sample before filter() (Alg. 1): none, the box mean along the ray
-// (Section 4.1) or the in-ray 3-axis Gaussian (Section 4.2).
-enum { kSmoothNone = 0, kSmoothBox = 1, kSmoothStar = 2 };
+// (Section 4.1) or the in-ray 3-axis Gaussian (Section 4.2).  kSmoothAuto compiles both none
+// and box into one kernel and picks per launch from box_arm.
+enum { kSmoothNone = 0, kSmoothBox = 1, kSmoothStar = 2, kSmoothAuto = 3 };
 
 // Run alive = per_sample(k, value, active) over the ray's samples k = 0 .. N-1, the value
 // being the raw sample, its box mean or its in-ray Gaussian.
@@ -288,22 +289,30 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 
 // One ray of Alg. 1 for pixel (px, py).  Every lane of the wave calls this (the march loop
 // is uniform); lanes outside the image pass inside = false and march no samples.  REUSE:
-// same-cell corner reuse (float32 storage at steps below a voxel).  STAR: the in-ray
-// Gaussian, compiled into kernels of its own so the others do not carry its registers.  NS:
+// same-cell corner reuse (float32 storage at steps below a voxel).  SMOOTH: the smoothing
+// compiled in; the one-image kernels compile each kind into kernels of their own, so the
+// plain march does not carry the registers of the box ring or the in-ray Gaussian.  NS:
 // fetch slots of the sample loop.  PACK: 16-bit corners stay packed while in flight.
 template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32,
-          bool STAR = false, int NS = drive_slots<MODE, DT>(), bool PACK = true>
+          int SMOOTH = kSmoothAuto, int NS = drive_slots<MODE, DT>(), bool PACK = true>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
     const Filt F = make_filter(a);
     const RaySeg r = pixel_ray(a, px, py, inside);
-    if (STAR)
+    if constexpr (SMOOTH == kSmoothStar) {
+        static_assert(RATIO == 0, "the in-ray Gaussian has no line-ratio form");
         march<MODE, 0, DT, C, WIDE, kSmoothStar, false, NS, PACK>(a, s_lut, ring, r, F, res, count);
-    else if (RATIO == 0 && a.p.box_arm > 0)
-        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
-    else
+    } else if constexpr (SMOOTH == kSmoothBox) {
+        static_assert(RATIO == 0, "the line-ratio methods take no box smoothing");
+        march<MODE, 0, DT, C, WIDE, kSmoothBox, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
+    } else if constexpr (SMOOTH == kSmoothNone) {
         march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
+    } else if (RATIO == 0 && a.p.box_arm > 0) {
+        march<MODE, RATIO, DT, C, WIDE, kSmoothBox, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
+    } else {
+        march<MODE, RATIO, DT, C, WIDE, kSmoothNone, REUSE, NS, PACK>(a, s_lut, ring, r, F, res, count);
+    }
 }
 
 // Pixel (lx, ly) of an 8x8 wave tile rendered by lane l.  The vector memory pipeline works

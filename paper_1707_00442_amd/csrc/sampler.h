@@ -301,9 +301,9 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
 template <int MODE, int DT>
 constexpr int drive_slots() {
     if (MODE == SVR_MIP0 || MODE == SVR_MIP1 || MODE == SVR_MIPRGB) return DT == SVR_F32 ? 6 : 8;
-    if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 4 : 7;
+    if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 5 : 7;
     if (MODE == SVR_AVIP0) return 6;
-    return DT == SVR_F32 ? 6 : 8;  // SVR_AVIP1
+    return DT == SVR_F32 ? 7 : 8;  // SVR_AVIP1
 }
 
 }  // namespace svr
