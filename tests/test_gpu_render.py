@@ -282,7 +282,9 @@ def test_half_storage_perspective(svr, storage, mode):
 
 def test_fp16_exact_cube_renders_bitwise_equal(svr):
     """A cube whose values are exactly representable in binary16 renders identically from
-    float16 and float32 storage (the arithmetic is float32 either way)."""
+    float16 and float32 storage (the arithmetic is float32 either way), with and without box
+    smoothing, below and at one voxel per step: float32 kernels with and without same-cell
+    reuse, and the plain, box and combined march kernels, against the packed 16-bit ones."""
     cube = quant.dequantize(synth.blob_cube_64(2), "f16")
     cam = synth.perspective_lookat(64, 64, 64, 10.0, 30.0, 140.0, 40.0, 96, 64).as_f32()
     lut = to_cuda(synth.lut_heat(256))
@@ -290,9 +292,33 @@ def test_fp16_exact_cube_renders_bitwise_equal(svr):
     b = _vol(svr, cube, "f16")
     lo, hi = quant.finite_minmax(cube)
     for mode in MODES:
-        ia = svr.svr_render(a, cam, lut, mode=mode, clim_lo=lo, clim_hi=hi)
-        ib = svr.svr_render(b, cam, lut, mode=mode, clim_lo=lo, clim_hi=hi)
-        assert torch_equal(ia, ib), mode
+        for box in (0, 2):
+            for dt in (0.5, 1.0):
+                kw = dict(mode=mode, clim_lo=lo, clim_hi=hi, box_arm=box, dt=dt, k=0.22)
+                ia = svr.svr_render(a, cam, lut, **kw)
+                ib = svr.svr_render(b, cam, lut, **kw)
+                assert torch_equal(ia, ib), (mode, box, dt)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("mode", ["mip0", "avip0", "aviprgb"])
+def test_half_storage_box(svr, ragged, storage, mode):
+    """FP16/BF16 storage with box smoothing along the ray (Section 4.1): <= 1e-5 against the
+    oracle on the stored values."""
+    cube, _, _, cam = ragged
+    deq = quant.dequantize(cube, storage)
+    lo, hi = quant.finite_minmax(deq)
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, k=0.31, box_arm=2)
+    print(f"[half box] storage={storage} mode={mode}", flush=True)
+    vol = _vol(svr, cube, storage=storage)
+    got, ns = gpu_render(svr, vol, cam, to_cuda(lut), params, lo, hi)
+    err, frag, _ = compare_render(oracle, got, ns, deq, cam, lut, params, lo, hi,
+                                  margins=margins(lo, hi, params), cond_tol=COND_TOL)
+    hit = int((ns > 0).sum())
+    print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
+    assert err <= TOL32
+    assert frag.sum() < 0.05 * hit and hit > 2000
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
