@@ -114,7 +114,7 @@ template <int MODE, int RATIO, int DT, int C, bool WIDE, int SMOOTH, bool REUSE,
 __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, float* ring,
                                       const RaySeg& r, const Filt& F, float4& res,
                                       int& count) {
-    using Smp = Sampler<DT, C, WIDE, REUSE, PACK>;
+    using Smp = Sampler<DT, C, WIDE, REUSE, PACK, oob_reuse<MODE, DT, WIDE, REUSE>()>;
     const Smp smp(a.v);
     const int N = r.n;
     const float n_lut = (float)(a.lut_n - 1);
@@ -294,7 +294,8 @@ __device__ __forceinline__ RaySeg pixel_ray(const RenderArgs& a, int px, int py,
 // plain march does not carry the registers of the box ring or the in-ray Gaussian.  NS:
 // fetch slots of the sample loop.  PACK: 16-bit corners stay packed while in flight.
 template <int MODE, int RATIO, int DT, int C, bool WIDE, bool REUSE = DT == SVR_F32,
-          int SMOOTH = kSmoothAuto, int NS = drive_slots<MODE, DT>(), bool PACK = true>
+          int SMOOTH = kSmoothAuto,
+          int NS = drive_slots<MODE, DT, oob_reuse<MODE, DT, WIDE, REUSE>()>(), bool PACK = true>
 __device__ __forceinline__ void render_ray(const RenderArgs& a, const float4* s_lut, float* ring,
                                            int px, int py, bool inside, float4& res,
                                            int& count) {
