@@ -329,7 +329,7 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
 
 // Same-cell reuse through out-of-range loads (Sampler, OOB) for float32 storage addressed
 // with 32-bit offsets: measured faster for the AVIP transfer functions (AVIP0 at 8 slots
-// 10% faster, AVIP1 5%, AVIP_RGB 2%) and slower for MIP, which keeps the branch.
+// 10% faster, AVIP1 at 9 slots 7%, AVIP_RGB 2%) and slower for MIP, which keeps the branch.
 template <int MODE, int DT, bool WIDE, bool REUSE>
 constexpr bool oob_reuse() {
     return REUSE && !WIDE && DT == SVR_F32 &&
@@ -345,7 +345,7 @@ constexpr int drive_slots() {
     if (MODE == SVR_MIP0 || MODE == SVR_MIP1 || MODE == SVR_MIPRGB) return DT == SVR_F32 ? 6 : 8;
     if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 5 : 7;
     if (MODE == SVR_AVIP0) return OOB ? 8 : 6;
-    return DT == SVR_F32 ? 7 : 8;  // SVR_AVIP1
+    return DT == SVR_F32 ? (OOB ? 9 : 7) : 8;  // SVR_AVIP1
 }
 
 }  // namespace svr
