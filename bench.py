@@ -179,7 +179,8 @@ def main():
     ratio_views = [v.as_f32() for v in synth.rotation_views(nx, ny, 32, W, H)]
     taps = {s: tapgen.gauss(float(s)).astype(np.float32) for s in (1, 2, 3)}
     smooth_out = torch.empty_like(cube)
-    ws = torch.empty(svr.svr_smooth_workspace(cube), dtype=torch.uint8, device="cuda")
+    ws = None  # the fused 7/13/19-tap passes need no workspace
+    assert all(svr.svr_smooth_workspace(cube, len(taps[s])) == 0 for s in taps)
     ratio_out = torch.empty((32, ny, nx), dtype=torch.float32, device="cuda")
     imgs = {m: torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for m in MODES}
     rimg = {r: torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for r in (1, 2)}

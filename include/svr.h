@@ -183,8 +183,10 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
  * with clamp-to-edge borders and float32 accumulation.  taps_host[ntaps] (odd ntaps <=
  * SVR_MAX_TAPS) is centred: out[x] = sum_j taps[j] * in[x + j - ntaps/2].  `in` must be
  * C-contiguous; `out` is C-contiguous with the same dims and dtype.  workspace: device
- * buffer of at least svr_smooth_workspace() bytes (two float32 cubes). */
-svr_status svr_smooth_workspace(const svr_cube_view* in, size_t* bytes);
+ * buffer of at least svr_smooth_workspace(in, ntaps) bytes: 0 for the tap counts with a
+ * fused single-pass kernel (5, 7, 9, 13, 19; workspace may then be NULL), two float32 cubes
+ * otherwise. */
+svr_status svr_smooth_workspace(const svr_cube_view* in, int32_t ntaps, size_t* bytes);
 svr_status svr_smooth(const svr_cube_view* in, const float* taps_host, int32_t ntaps,
                       void* out, void* workspace, size_t workspace_bytes, void* stream);
 

@@ -230,10 +230,12 @@ def svr_render(vol, camera, lut, params=None, vol2=None, out=None, samples=False
 
 
 # ------------------------------------------------------------------------------- smoothing
-def svr_smooth_workspace(cube):
+def svr_smooth_workspace(cube, ntaps):
+    """Device bytes of workspace svr_smooth needs for `ntaps` taps (0 for the fused kernels)."""
     v = cube_view(cube)
     n = C.c_size_t()
-    _check(lib().svr_smooth_workspace(C.byref(v), C.byref(n)), "svr_smooth_workspace")
+    _check(lib().svr_smooth_workspace(C.byref(v), int(ntaps), C.byref(n)),
+           "svr_smooth_workspace")
     return n.value
 
 
@@ -242,12 +244,13 @@ def svr_smooth(cube, taps, out=None, workspace=None, stream=None):
     g = (C.c_float * len(taps))(*[float(x) for x in taps])
     if out is None:
         out = torch.empty_like(cube, memory_format=torch.contiguous_format)
-    need = svr_smooth_workspace(cube)
-    if workspace is None:
+    need = svr_smooth_workspace(cube, len(taps))
+    if workspace is None and need > 0:
         workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
-    _check(lib().svr_smooth(C.byref(v), g, len(taps), C.c_void_p(out.data_ptr()),
-                            C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
-                            _stream(stream)), "svr_smooth")
+    ws_ptr = C.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().svr_smooth(C.byref(v), g, len(taps), C.c_void_p(out.data_ptr()), ws_ptr,
+                            ws_bytes, _stream(stream)), "svr_smooth")
     return out
 
 

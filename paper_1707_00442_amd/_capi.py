@@ -82,7 +82,7 @@ def load():
         "svr_volume_export": (C.c_int, [vp, vp, vp]),
         "svr_params_validate": (C.c_int, [P(Params)]),
         "svr_render": (C.c_int, [vp, vp, P(Camera), P(Lut), P(Params), vp, vp, vp]),
-        "svr_smooth_workspace": (C.c_int, [P(CubeView), P(C.c_size_t)]),
+        "svr_smooth_workspace": (C.c_int, [P(CubeView), i32, P(C.c_size_t)]),
         "svr_smooth": (C.c_int, [P(CubeView), P(f32), i32, vp, vp, C.c_size_t, vp]),
         "svr_line_ratio": (C.c_int, [P(CubeView), i32, i32, i32, f32, f32, f32, vp, vp]),
         "svr_moments": (C.c_int, [P(CubeView), i32, i32, f32, f32, f32, vp, vp, vp, vp]),

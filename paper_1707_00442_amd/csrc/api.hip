@@ -38,6 +38,7 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
                          int32_t* samples, hipStream_t stream);
 svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int ntaps, void* out,
                          void* ws, hipStream_t stream);
+bool smooth_fused_taps(int ntaps);
 svr_status launch_moments(const svr_cube_view& c, int z0, int nzw, float dv, float lo, float hi,
                           float* m0, float* m1, int32_t* amax, hipStream_t stream);
 svr_status launch_line_ratio(const svr_cube_view& c, int z0a, int z0b, int nzw, float min_a,
@@ -296,11 +297,13 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
                          samples_out, S(stream));
 }
 
-svr_status svr_smooth_workspace(const svr_cube_view* in, size_t* bytes) {
+svr_status svr_smooth_workspace(const svr_cube_view* in, int32_t ntaps, size_t* bytes) {
     svr_status st = check_view(in, "svr_smooth_workspace");
     if (st) return st;
     SVR_CHECK(bytes != nullptr, "null output");
-    *bytes = 2 * (size_t)view_elems_span(in) * sizeof(float);
+    SVR_CHECK(ntaps >= 1 && ntaps <= SVR_MAX_TAPS && (ntaps % 2) == 1,
+              "svr_smooth_workspace: ntaps = %d (odd, <= %d)", ntaps, SVR_MAX_TAPS);
+    *bytes = smooth_fused_taps(ntaps) ? 0 : 2 * (size_t)view_elems_span(in) * sizeof(float);
     return SVR_OK;
 }
 
@@ -317,11 +320,14 @@ svr_status svr_smooth(const svr_cube_view* in, const float* taps_host, int32_t n
               "svr_smooth: ntaps = %d (odd, <= %d)", ntaps, SVR_MAX_TAPS);
     for (int j = 0; j < ntaps; ++j)
         SVR_CHECK(isfinite(taps_host[j]), "svr_smooth: tap %d not finite", j);
-    SVR_CHECK(out != nullptr && workspace != nullptr, "svr_smooth: null out/workspace");
+    SVR_CHECK(out != nullptr, "svr_smooth: null output");
     SVR_CHECK(out != in->data, "svr_smooth: out must not alias the input");
-    SVR_CHECK((int64_t)in->ny * in->nz < (1ll << 31) && in->nz <= 65535,
+    SVR_CHECK((int64_t)in->ny * in->nz < (1ll << 31) && in->nz <= 65535 &&
+                  (int64_t)in->nx * in->ny < (1ll << 31),
               "svr_smooth: cube too large for the launch grid");
-    const size_t need = 2 * (size_t)view_elems_span(in) * sizeof(float);
+    const size_t need =
+        smooth_fused_taps(ntaps) ? 0 : 2 * (size_t)view_elems_span(in) * sizeof(float);
+    SVR_CHECK(need == 0 || workspace != nullptr, "svr_smooth: null workspace");
     if (workspace_bytes < need) {
         set_error("svr_smooth: workspace %zu < %zu bytes", workspace_bytes, need);
         return SVR_ENOMEM;
@@ -335,7 +341,8 @@ svr_status svr_line_ratio(const svr_cube_view* cube, int32_t z0_a, int32_t z0_b,
     svr_status st = check_view(cube, "svr_line_ratio");
     if (st) return st;
     SVR_CHECK(nz_w >= 1 && nz_w <= 65535, "svr_line_ratio: window length %d", nz_w);
-    SVR_CHECK(z0_a >= 0 && z0_b >= 0 && z0_a + nz_w <= cube->nz && z0_b + nz_w <= cube->nz,
+    SVR_CHECK(z0_a >= 0 && z0_b >= 0 && (int64_t)z0_a + nz_w <= cube->nz &&
+                  (int64_t)z0_b + nz_w <= cube->nz,
               "svr_line_ratio: windows [%d, %d) and [%d, %d) outside 0..%d", z0_a, z0_a + nz_w,
               z0_b, z0_b + nz_w, cube->nz);
     SVR_CHECK(cube->ny <= 65535, "svr_line_ratio: ny too large for the launch grid");

@@ -199,10 +199,16 @@ __device__ __forceinline__ float4 table(const float4* L, float nm1, float s) {
 }
 
 // Host side helpers --------------------------------------------------------------------
-// True when a volume's bricked storage spans more than 2^32 bytes (64-bit addressing).
+// Byte offset past the end of every storage addressed with 32-bit offsets: buffer loads
+// there return 0 without a memory access (the out-of-range reuse loads of the sampler).
+constexpr uint32_t kPastStorage = 0xfffff000u;
+
+// True when a volume's bricked storage is addressed with 64-bit offsets: storage that
+// reaches kPastStorage bytes (so that 32-bit offsets from kPastStorage on always lie past
+// its end).
 inline bool wide_volume(const VolDesc& d) {
     const uint64_t esize = d.dtype == SVR_F32 ? 4 : 2;
-    return (uint64_t)d.nbx * d.nby * d.nbz * d.pitch * esize > 0xffffffffull;
+    return (uint64_t)d.nbx * d.nby * d.nbz * d.pitch * esize > (uint64_t)kPastStorage;
 }
 
 void set_error(const char* fmt, ...);

@@ -111,11 +111,12 @@ struct Sampler {
         last = o;
         if constexpr (kOob) {
             // Reuse without a branch: a repeated cell's loads are issued at an offset past
-            // the end of any 32-bit addressed storage, where buffer loads return 0 without
+            // the end of any 32-bit addressed storage (such storage ends below kPastStorage,
+            // larger volumes take the 64-bit path), where buffer loads return 0 without
             // touching memory.  Every sample then issues the same four loads, so the loads
             // of later samples stay in flight while this one is blended (behind a branch the
             // waits before each blend must assume none were issued).
-            constexpr uint32_t kPast = 0xfffff000u;
+            constexpr uint32_t kPast = kPastStorage;
             const uint32_t b = f.reuse ? kPast : o * 4u;
             const auto p0 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, b, 0, 0);
             const auto p1 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, b + 4u * E, 0, 0);

@@ -303,6 +303,11 @@ static svr_status smooth_fixed(const svr_cube_view& c, const float* taps_host, v
     }
 }
 
+// Tap counts with a fused kernel (no intermediate cube, no workspace).
+bool smooth_fused_taps(int ntaps) {
+    return ntaps == 5 || ntaps == 7 || ntaps == 9 || ntaps == 13 || ntaps == 19;
+}
+
 svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int ntaps, void* out,
                          void* ws, hipStream_t stream) {
     switch (ntaps) {

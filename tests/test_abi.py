@@ -104,8 +104,19 @@ def test_smooth_and_ratio_validation(capi):
     v = _fake_view(capi)
     taps = (C.c_float * 4)(0.25, 0.25, 0.25, 0.25)
     n = C.c_size_t()
-    assert L.svr_smooth_workspace(C.byref(v), C.byref(n)) == capi.SVR_OK
+    assert L.svr_smooth_workspace(C.byref(v), 3, C.byref(n)) == capi.SVR_OK
     assert n.value == 2 * 8 * 8 * 8 * 4
+    # the fused tap counts need no workspace (and accept none)
+    for T in (5, 7, 9, 13, 19):
+        m = C.c_size_t(123)
+        assert L.svr_smooth_workspace(C.byref(v), T, C.byref(m)) == capi.SVR_OK
+        assert m.value == 0
+    assert L.svr_smooth_workspace(C.byref(v), 4, C.byref(n)) == capi.SVR_EINVAL
+    taps7 = (C.c_float * 7)(*([1.0 / 7] * 7))
+    assert L.svr_smooth(C.byref(v), taps7, 7, None, None, 0, None) == capi.SVR_EINVAL
+    assert L.svr_smooth(C.byref(v), taps7, 7, C.c_void_p(0x1000), None, 0,
+                        None) == capi.SVR_EINVAL  # output aliases the input
+    n.value = 2 * 8 * 8 * 8 * 4
     assert L.svr_smooth(C.byref(v), taps, 4, C.c_void_p(0x5000), C.c_void_p(0x6000), n.value,
                         None) == capi.SVR_EINVAL  # even tap count
     taps3 = (C.c_float * 3)(0.25, 0.5, 0.25)
@@ -118,6 +129,14 @@ def test_smooth_and_ratio_validation(capi):
                             None) == capi.SVR_EINVAL  # window 4..9 leaves the cube
     assert L.svr_line_ratio(C.byref(v), 0, 4, 4, math.nan, 0.0, -1.0, C.c_void_p(0x5000),
                             None) == capi.SVR_EINVAL
+    # window starts near INT32_MAX: the end is checked in 64 bits (no overflow)
+    big = 2 ** 31 - 2
+    assert L.svr_line_ratio(C.byref(v), big, 0, 4, 0.0, 0.0, -1.0, C.c_void_p(0x5000),
+                            None) == capi.SVR_EINVAL
+    assert L.svr_line_ratio(C.byref(v), 0, big, 4, 0.0, 0.0, -1.0, C.c_void_p(0x5000),
+                            None) == capi.SVR_EINVAL
+    assert L.svr_moments(C.byref(v), big, 4, 1.0, -math.inf, math.inf, C.c_void_p(0x5000),
+                         None, None, None) == capi.SVR_EINVAL
 
 
 def test_status_strings(capi):
