@@ -72,6 +72,19 @@ typedef struct {
  * lo_hi_host[2]; if no value is finite both are NaN.  Synchronises `stream`. */
 svr_status svr_minmax(const svr_cube_view* cube, float* lo_hi_host, void* stream);
 
+/* Allocation-free variant of svr_minmax, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The same finite minimum and maximum as svr_minmax, written to lo_hi_dev[2] in DEVICE
+ * memory owned by the caller, asynchronously on `stream` (no copy to the host, no
+ * synchronisation).  It calls no hipMalloc, hipFree or other allocating routine: the
+ * per-workgroup partials of the reduction live in a fixed library array of 3 x 2048 floats
+ * (24 KiB) on each GPU, set up on the first call on that GPU and held until the process
+ * ends.  The reduction never uses more than 2048 workgroups, so every cube size fits;
+ * SVR_EINVAL (with a message) if a launch would need more partials than the array holds.
+ * Calls that overlap on one GPU share the array and race: serialise them (one stream, or
+ * events between streams). */
+svr_status svr_minmax_noalloc(const svr_cube_view* cube, float* lo_hi_dev, void* stream);
+
 /* ---------------------------------------------------------------- volumes (upload)
  * A volume is the library's copy of a cube laid out for the ray-march: cubic bricks of
  * `brick` voxels per edge, each stored with a one-voxel apron on its +x/+y/+z faces (so a

@@ -206,6 +206,18 @@ def svr_minmax(cube, stream=None):
     return float(out[0]), float(out[1])
 
 
+def svr_minmax_noalloc(cube, out, stream=None):
+    """Allocation-free finite min/max into `out` (a float32 CUDA tensor of 2 elements),
+    asynchronous on the stream."""
+    v = cube_view(cube)
+    _cuda(out, "out")
+    if out.dtype != torch.float32 or out.numel() < 2 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 tensor of at least 2 elements")
+    _check(lib().svr_minmax_noalloc(C.byref(v), C.c_void_p(out.data_ptr()), _stream(stream)),
+           "svr_minmax_noalloc")
+    return out
+
+
 # ------------------------------------------------------------------------------- render
 def svr_params_validate(params=None, **kw):
     p = params_struct(params, **kw)

@@ -17,7 +17,7 @@ SVR_MAX_TAPS = 63
 
 # every symbol include/svr.h declares
 EXPORTS = (
-    "svr_status_string", "svr_last_error", "svr_version", "svr_minmax",
+    "svr_status_string", "svr_last_error", "svr_version", "svr_minmax", "svr_minmax_noalloc",
     "svr_volume_create", "svr_volume_destroy", "svr_volume_upload", "svr_volume_info",
     "svr_volume_clim",
     "svr_volume_export", "svr_params_validate", "svr_render", "svr_smooth_workspace",
@@ -74,6 +74,7 @@ def load():
         "svr_last_error": (C.c_char_p, []),
         "svr_version": (C.c_char_p, []),
         "svr_minmax": (C.c_int, [P(CubeView), P(f32), vp]),
+        "svr_minmax_noalloc": (C.c_int, [P(CubeView), vp, vp]),
         "svr_volume_create": (C.c_int, [P(CubeView), i32, i32, f32, vp, P(vp)]),
         "svr_volume_destroy": (C.c_int, [vp]),
         "svr_volume_upload": (C.c_int, [vp, P(CubeView), f32, vp]),

@@ -30,6 +30,7 @@ svr_status hip_fail(hipError_t e, const char* what) {
 size_t minmax_partial_floats();
 svr_status launch_minmax(const svr_cube_view& c, float* partial, float* out, int raw,
                          int out_dtype, float nan_fill, hipStream_t stream);
+svr_status launch_minmax_noalloc(const svr_cube_view& c, float* out, hipStream_t stream);
 svr_status launch_export(const VolDesc& d, void* out, hipStream_t stream);
 svr_status launch_upload(const svr_cube_view& c, const VolDesc& d, float* aux, float nan_fill,
                          hipStream_t stream);
@@ -168,6 +169,13 @@ svr_status svr_minmax(const svr_cube_view* cube, float* lo_hi_host, void* stream
     if (!st) st = hip_fail(hipStreamSynchronize(S(stream)), "svr_minmax sync");
     (void)hipFree(buf);
     return st;
+}
+
+svr_status svr_minmax_noalloc(const svr_cube_view* cube, float* lo_hi_dev, void* stream) {
+    svr_status st = check_view(cube, "svr_minmax_noalloc");
+    if (st) return st;
+    SVR_CHECK(lo_hi_dev != nullptr, "svr_minmax_noalloc: null output");
+    return launch_minmax_noalloc(*cube, lo_hi_dev, S(stream));
 }
 
 svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t brick,

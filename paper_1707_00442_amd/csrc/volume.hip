@@ -2,6 +2,8 @@
 // + min/max), and export back to a linear cube.  All stream the cube once; HBM-bound.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace svr {
@@ -481,6 +483,55 @@ svr_status launch_minmax(const svr_cube_view& c, float* partial, float* out, int
                                nparts, raw, nan_fill, out);
     }
     return hip_fail(hipGetLastError(), "minmax launch");
+}
+
+// ------------------------------------------------------------ allocation-free min/max
+// svr_minmax_noalloc keeps the per-workgroup partials of the reduction in this file-scope
+// device array instead of a buffer from hipMalloc.  Every GPU the library runs on holds its
+// own copy until the process ends.  In host code the name `scratch` is only a stand-in for
+// the symbol: its device address is looked up once per device, with that device current,
+// and only that address is handed to kernels.  The reduction never launches more than
+// kMinmaxMaxBlocks workgroups, each writing its own partial before the final kernel reads
+// it, so nothing in the array has to start at zero.  Calls that overlap on one GPU share
+// the array and race.
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) float scratch[3 * kMinmaxMaxBlocks];
+static float* g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static svr_status scratch_ptr(float** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "svr_minmax_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("svr_minmax_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+        return SVR_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "svr_minmax_noalloc: hipGetSymbolAddress");
+        g_scratch[dev] = static_cast<float*>(p);
+    }
+    *ptr = g_scratch[dev];
+    return SVR_OK;
+}
+
+svr_status launch_minmax_noalloc(const svr_cube_view& c, float* out, hipStream_t stream) {
+    int64_t nx, nrows, ny, sx, sy, sz;
+    dim3 grid;
+    minmax_grid(c, nx, nrows, ny, sx, sy, sz, grid);
+    const uint64_t parts = (uint64_t)grid.x * grid.y;
+    if (3 * parts > sizeof(scratch) / sizeof(float)) {
+        set_error("svr_minmax_noalloc: %llu partials exceed the %d the scratch array holds",
+                  (unsigned long long)parts, kMinmaxMaxBlocks);
+        return SVR_EINVAL;
+    }
+    float* partial = nullptr;
+    svr_status st = scratch_ptr(&partial);
+    if (st) return st;
+    return launch_minmax(c, partial, out, 1, SVR_F32, NAN, stream);
 }
 
 svr_status launch_export(const VolDesc& d, void* out, hipStream_t stream) {
