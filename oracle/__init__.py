@@ -52,6 +52,7 @@ class _Margins(C.Structure):
 
 
 FRAG_COUNT, FRAG_ARGMAX, FRAG_ERT, FRAG_THRESHOLD, FRAG_RATIO, FRAG_COND = 1, 2, 4, 8, 16, 32
+NOT_CANDIDATE = 64
 
 
 _lib = None
@@ -153,7 +154,8 @@ def render(cube, camera, lut, params, cube2=None, pixels=None, margins=None, nth
            forced_n=None, bits=False):
     """FP64 render.  Returns (rgba[npix,4] float64, fragile[npix], nsamples[npix]);
     fragile is boolean, or the FRAG_* bit mask when bits=True.  forced_n[npix] (>= 0)
-    makes AVIP rays composite exactly that many samples."""
+    makes AVIP rays composite exactly that many samples, and MIP1 / MIP_RGB rays take that
+    sample as the arg-max (NOT_CANDIDATE set when it is not within ds of the maximum)."""
     V = _cube64(cube)
     V2 = _cube64(cube2) if cube2 is not None else None
     if V2 is not None and V2.shape != V.shape:
@@ -252,7 +254,7 @@ def line_ratio(cube, z0a, z0b, nzw, min_t_a=-np.inf, min_t_b=-np.inf, datamin=0.
 
 
 def moments(cube, z0=0, nzw=None, dv=1.0, min_t=-np.inf, max_t=np.inf):
-    """Moment maps (Section 2.1, Eq. mom0 / Eq. mom1 and the argmax variant) of each spectrum
+    """Moment maps (Section 2.2, Eq. mom0 / Eq. mom1 and the argmax variant) of each spectrum
     over channels [z0, z0 + nzw): (m0, m1, argmax), each [ny, nx]."""
     V = _cube64(cube)
     nz, ny, nx = V.shape

@@ -327,6 +327,12 @@ static void render_core(const ray_ctx* base, const orc_camera* cam, int32_t px, 
                 fragile |= ORC_FRAG_ARGMAX;
                 break;
             }
+            /* The other reading of a near tie: any sample within ds of the maximum is an
+             * arg-max the '>=' of Eq. MIP could have kept under rounding. */
+            if (forced >= 0) {
+                if (forced >= N || smax - sbuf[forced] >= mg->ds) fragile |= ORC_NOT_CANDIDATE;
+                if (forced < N) kmax = forced;
+            }
         }
         double alpha;
         if (p->mode == ORC_MIP0) {
@@ -347,8 +353,8 @@ static void render_core(const ray_ctx* base, const orc_camera* cam, int32_t px, 
         if (p->mip_alpha == 1) {
             alpha = 1.0;
         } else if (p->mip_alpha == 2) {
-            /* Section 5.4 workaround: transparent only where the maximum is at or below
-             * the minimum threshold, opaque elsewhere. */
+            /* Workaround of the Discussion (Section 5.7): transparent only where the
+             * maximum is at or below the minimum threshold, opaque elsewhere. */
             double sthr = domain01(p->min_t, p->lo, p->hi);
             if (fabs(smax - sthr) < mg->ds) fragile |= ORC_FRAG_ARGMAX;
             if (smax > sthr) alpha = 1.0;
@@ -696,7 +702,7 @@ int orc_line_ratio(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t 
     return 0;
 }
 
-/* Section 2.1: the zeroth moment integrates each spectrum (Eq. mom0, the channel sum times the
+/* Section 2.2: the zeroth moment integrates each spectrum (Eq. mom0, the channel sum times the
  * channel width), the first moment is its intensity-weighted mean channel (Eq. mom1), and the
  * argmax variant returns the channel of the spectrum's maximum.  Readings: channels that are
  * not finite or fall outside [min_t, max_t] do not count (like clipped samples); ties in the

@@ -77,7 +77,9 @@ enum {
     ORC_FRAG_ERT = 4,        /* AVIP: alpha within da of the termination threshold */
     ORC_FRAG_THRESHOLD = 8,  /* a filtered value within dv of minT/maxT (or of 0 for ratios) */
     ORC_FRAG_RATIO = 16,     /* ratio denominator below dr */
-    ORC_FRAG_COND = 32       /* the +-pv / +-pp probe moved the RGBA by more than pt */
+    ORC_FRAG_COND = 32,      /* the +-pv / +-pp probe moved the RGBA by more than pt */
+    ORC_NOT_CANDIDATE = 64   /* forced arg-max: the forced sample is not within ds of the
+                                maximum (so it is not a valid arg-max) */
 };
 
 /* Render npix pixels (pix == NULL: all width*height pixels, row-major).  V2 is the second
@@ -85,7 +87,10 @@ enum {
  * Outputs rgba[4*npix], fragile[npix] (ORC_FRAG_* bits), nsamples[npix] (may be NULL).
  * forced_n (may be NULL): per pixel, when >= 0 an AVIP ray composites exactly that many
  * samples instead of stopping at the threshold (the other reading of a near-threshold
- * termination).  Returns 0 on success, nonzero on invalid arguments. */
+ * termination), and a MIP1 / MIP_RGB ray takes sample forced_n as its arg-max (the other
+ * reading of a near tie of the maximum; ORC_NOT_CANDIDATE flags a sample further than ds
+ * below the maximum, or past the ray's end).  Returns 0 on success, nonzero on invalid
+ * arguments. */
 int orc_render(const double* V, const double* V2, int32_t nx, int32_t ny, int32_t nz,
                const orc_camera* cam, const double* lut, int32_t M, const orc_params* p,
                const orc_margins* mg, int64_t npix, const int64_t* pix,
@@ -122,7 +127,7 @@ int orc_line_ratio(const double* V, int32_t nx, int32_t ny, int32_t nz, int32_t 
                    int32_t z0b, int32_t nzw, double min_t_a, double min_t_b, double datamin,
                    double* out);
 
-/* Moment maps of every spectrum over channels [z0, z0 + nzw) (Section 2.1, Eq. mom0 and
+/* Moment maps of every spectrum over channels [z0, z0 + nzw) (Section 2.2, Eq. mom0 and
  * Eq. mom1, and the argmax variant).  A channel counts when its value is finite and inside
  * [min_t, max_t].  m0 = dv * sum v; m1 = sum z v / sum v with z the cube's channel index (NaN
  * when no channel counts or the sum is zero); amax = the last channel holding the largest

@@ -559,7 +559,7 @@ def test_finite_minmax_ignores_nan():
     assert lo == f.min() and hi == f.max() and np.isnan(cube).any()
 
 
-# ------------------------------------------------------------------ moment maps (Section 2.1)
+# ------------------------------------------------------------------ moment maps (Section 2.2)
 def _gauss_line_cube(nx, ny, nz, seed):
     """Each spectrum one Gaussian line A exp(-(z - mu)^2 / 2 s^2), s = 3 channels, with mu at
     least 10 s from both ends: the channel sums equal the integrals up to terms below 1e-20
@@ -709,3 +709,187 @@ def test_star_linear_sampling_at_voxel_centres():
     F = _one_axis(f, t, c0, pairs)
     direct = np.array([sum(g[j] * f[int(ti) + j - 4] for j in range(9)) for ti in t])
     assert np.max(np.abs(F - direct)) < 1e-9
+
+
+# ------------------------------------------------------------------ branches pinned by closed forms
+def _pinhole_pixel(cam, point):
+    """Continuous pixel coordinates of a world point under a pinhole camera whose axes
+    U, V are orthogonal to the unit viewing direction W: the point's offset from the eye,
+    divided by its depth along W, has components u |U| and v |V| across the image, and
+    pixel centres sit at u = 2 (px + 0.5)/width - 1 (inverted here)."""
+    r = np.asarray(point, np.float64) - np.asarray(cam.eye, np.float64)
+    U, V, W = (np.asarray(a, np.float64) for a in (cam.U, cam.V, cam.W))
+    depth = float(r @ W)
+    u = float(r @ U) / float(U @ U) / depth
+    v = float(r @ V) / float(V @ V) / depth
+    return (u + 1.0) * cam.width / 2.0 - 0.5, (v + 1.0) * cam.height / 2.0 - 0.5
+
+
+@pytest.mark.parametrize("az,el", [(0.0, 0.0), (40.0, 20.0), (130.0, -35.0), (220.0, 60.0),
+                                   (300.0, 10.0)])
+def test_perspective_bright_voxel_lands_on_pinhole_pixel(az, el):
+    """Appendix A perspective projection, orientation: a single bright voxel off the
+    viewing axis lights the pixel the pinhole model predicts for the look-at camera (u to
+    the camera's right along U, v along V; a mirrored, rotated or u/v-swapped image moves
+    the brightest pixel far from the prediction).  MIP0 of a zero cube with one voxel at 1:
+    the brightest ray is the one passing nearest the voxel centre."""
+    nx, ny, nz = 24, 20, 28
+    W, H = 64, 48
+    lut = synth.lut_ramp(256)
+    cam = synth.perspective_lookat(nx, ny, nz, az, el, 48.0, 30.0, W, H)
+    checked = 0
+    for vox in [(18, 5, 9), (4, 15, 20), (15, 13, 3)]:
+        cube = np.zeros((nz, ny, nx), np.float32)
+        cube[vox[2], vox[1], vox[0]] = 1.0
+        rgba, _, _ = oracle.render(cube, cam, lut, dict(mode="mip0", lo=0.0, hi=1.0, dt=0.05))
+        img = rgba[:, 0].reshape(H, W)
+        py, px = np.unravel_index(int(np.argmax(img)), img.shape)
+        ex, ey = _pinhole_pixel(cam, vox)
+        # the voxel must project well away from the image centre for this to pin orientation
+        assert abs(ex - (W - 1) / 2) + abs(ey - (H - 1) / 2) > 6
+        assert abs(px - ex) <= 1.0 and abs(py - ey) <= 1.0, (vox, (px, py), (ex, ey))
+        assert img.max() > 0.5  # a ray passes within half a pixel (~0.2 voxel) of the centre
+        checked += 1
+    assert checked == 3
+
+
+def test_perspective_centre_ray_and_field_of_view():
+    """Appendix A perspective rays: on an image of odd size the centre pixel's ray runs
+    along W through the look-at point (the cube centre), and the rays through the outer
+    pixel centres of the middle column (row) subtend 2 atan(tan(fov/2) (1 - 1/H)) (and
+    2 atan(tan(fov/2) (W/H) (1 - 1/W)) across), the field of view of the look-at camera
+    less half a pixel at each edge."""
+    nx, ny, nz = 30, 22, 40
+    W, H, fov = 65, 33, 36.0
+    cam = synth.perspective_lookat(nx, ny, nz, 25.0, 15.0, 70.0, fov, W, H)
+    centre = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2])
+    o, d = oracle.pixel_ray(cam, W // 2, H // 2)
+    assert np.allclose(o, cam.eye)
+    # distance from the cube centre to the centre ray
+    w = centre - o
+    assert np.linalg.norm(w - (w @ d) * d) < 1e-9
+    assert abs(np.linalg.norm(d) - 1.0) < 1e-14
+
+    def angle(a, b):
+        return math.acos(max(-1.0, min(1.0, float(a @ b))))
+    t = math.tan(math.radians(fov) / 2)
+    _, d_lo = oracle.pixel_ray(cam, W // 2, 0)
+    _, d_hi = oracle.pixel_ray(cam, W // 2, H - 1)
+    assert abs(angle(d_lo, d_hi) - 2 * math.atan(t * (1 - 1 / H))) < 1e-12
+    _, d_l = oracle.pixel_ray(cam, 0, H // 2)
+    _, d_r = oracle.pixel_ray(cam, W - 1, H // 2)
+    assert abs(angle(d_l, d_r) - 2 * math.atan(t * (W / H) * (1 - 1 / W))) < 1e-12
+    # rows and columns move along V and U respectively (not swapped, not mirrored)
+    U, V = np.asarray(cam.U), np.asarray(cam.V)
+    assert (d_hi - d_lo) @ V > 0 and abs((d_hi - d_lo) @ U) < 1e-12
+    assert (d_r - d_l) @ U > 0 and abs((d_r - d_l) @ V) < 1e-12
+
+
+def test_avip_all_transparent_ray_ends_at_min_val():
+    """Alg. AVIP0's minVal: a ray whose samples are all at DATAMIN (s = 0, no opacity) has
+    alpha1 + alpha2 = 0 at every sample, so alpha is held at minVal and the colour stays 0:
+    the fragment is (0, 0, 0, minVal) for any minVal, in every AVIP colouring."""
+    n = 16
+    cube = np.full((n, n, n), 2.0, np.float32)
+    cam = synth.ortho_axis(n, n, n, 8, 8, "+z")
+    lut = synth.lut_heat(256)
+    for mode in ("avip0", "avip1", "aviprgb"):
+        for mv in (1e-6, 0.3):
+            rgba, _, ns = oracle.render(cube, cam, lut, dict(mode=mode, lo=2.0, hi=3.0,
+                                                             k=0.5, min_val=mv))
+            assert (ns == 2 * n).all()
+            assert np.all(rgba[:, :3] == 0.0)
+            assert np.all(rgba[:, 3] == mv)
+
+
+def test_avip_min_val_clamp_closed_form():
+    """Alg. AVIP0's minVal clamp when the first sample's opacity a = k s is below minVal:
+    alpha_1 = max(a, minVal) = minVal and the first colour weight is a/minVal; afterwards
+    1 - alpha_n = (1 - minVal)(1 - a)^(n-1), and the premultiplied colour grows by
+    c a (1 - alpha_{n-1}) per sample, so rgb_n = c (a + alpha_n - minVal)/alpha_n."""
+    n = 64
+    cube = np.full((n, n, n), 0.5, np.float32)
+    cam = synth.ortho_axis(n, n, n, 4, 4, "+z")
+    lut = synth.lut_heat(256)
+    mv, k = 0.05, 0.01
+    a = k * 0.5
+    rgba, frag, ns = oracle.render(cube, cam, lut, dict(mode="avip0", lo=0.0, hi=1.0, k=k,
+                                                        min_val=mv))
+    N = 128
+    assert (ns == N).all()
+    alpha = 1.0 - (1.0 - mv) * (1.0 - a) ** (N - 1)
+    c = np.array([np.interp(0.5, np.arange(256) / 255.0, lut[:, ch].astype(np.float64))
+                  for ch in range(3)])
+    assert np.max(np.abs(rgba[:, 3] - alpha)) < 1e-12
+    assert np.max(np.abs(rgba[:, :3] - c[None] * (a + alpha - mv) / alpha)) < 1e-12
+    # the clamp really changed the result: without it the colour would be c exactly
+    assert np.min(np.abs(rgba[:, 0] - c[0])) > 1e-3
+
+
+@pytest.mark.parametrize("mode", ["mip0", "mip1", "miprgb"])
+def test_mip_alpha_workaround_closed_form(mode):
+    """The Discussion's transparency workaround (mip_alpha = 2): a fragment is opaque where
+    the ray's maximum exceeds minThreshold, and keeps the plain MIP alpha (s_max for MIP1
+    and MIP_RGB, the table's alpha at s_max for MIP0) where it does not.  Axis-aligned rays
+    through voxel centres see s_max = (max_z V - lo)/(hi - lo) exactly."""
+    n = 16
+    rng = np.random.default_rng(21)
+    cube = rng.uniform(0.0, 0.7, (n, n, n)).astype(np.float32)
+    hot = rng.random((n, n)) < 0.5
+    zi = rng.integers(0, n, (n, n))
+    yy, xx = np.nonzero(hot)
+    cube[zi[yy, xx], yy, xx] = rng.uniform(0.805, 1.0, yy.size).astype(np.float32)
+    min_t = float(np.float32(0.8))
+    # maxima just below the threshold, and exactly at it (not above: stays transparent)
+    cube[3, 0, :6] = np.linspace(0.77, 0.795, 6).astype(np.float32)
+    cube[5, 1, :4] = np.float32(min_t)
+    cube[:, 0, :6] = np.minimum(cube[:, 0, :6], cube[3, 0, :6][None])
+    cube[:, 1, :4] = np.minimum(cube[:, 1, :4], np.float32(min_t))
+    lut = synth.lut_heat(256)
+    lut[:, 3] = np.sqrt(np.arange(256) / 255.0)  # table alpha distinct from s
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    rgba, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=0.0, hi=1.0, mip_alpha=2,
+                                                    min_t=min_t))
+    smax = cube.astype(np.float64).max(axis=0).ravel()
+    above = smax > min_t
+    assert above.any() and (~above).any()
+    assert (smax == min_t).sum() == 4 and ((smax > 0.765) & (smax < 0.8)).sum() == 6
+    if mode == "mip0":
+        plain = np.interp(smax, np.arange(256) / 255.0, lut[:, 3].astype(np.float64))
+    else:
+        plain = smax
+    expect = np.where(above, 1.0, plain)
+    assert np.max(np.abs(rgba[:, 3] - expect)) < 1e-12
+    # the other settings: plain alpha (0) and always opaque (1)
+    r0, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=0.0, hi=1.0, mip_alpha=0))
+    r1, _, _ = oracle.render(cube, cam, lut, dict(mode=mode, lo=0.0, hi=1.0, mip_alpha=1))
+    assert np.max(np.abs(r0[:, 3] - plain)) < 1e-12
+    assert np.all(r1[:, 3] == 1.0)
+
+
+def test_ratio_method1_nonpositive_denominator_gives_zero():
+    """Alg. line ratio, method 1: the fragment is colourMap(max2/max1) only where the first
+    cube's maximum along the ray is positive; a ray whose max1 is 0 or negative gives
+    (0, 0, 0, 0) whatever the second cube holds.  Axis-aligned rays through voxel centres
+    see max_i = max_z V_i exactly."""
+    n = 12
+    rng = np.random.default_rng(5)
+    v1 = rng.uniform(0.2, 1.0, (n, n, n))
+    v2 = rng.uniform(0.1, 0.9, (n, n, n))
+    v1[:, :4, :] = -rng.uniform(0.1, 1.0, (n, 4, n))     # max1 < 0
+    v1[:, 4:6, :] = 0.0                                  # max1 = 0
+    v1[:, 4:6, :3] = -0.5                                # still max1 = 0 for x >= 3
+    v1, v2 = v1.astype(np.float32), v2.astype(np.float32)
+    cam = synth.ortho_axis(n, n, n, n, n, "+z")
+    lut = synth.lut_heat(64)
+    rgba, _, _ = oracle.render(v1, cam, lut, dict(mode="mip0", ratio=1, ratio_lo=0.0,
+                                                  ratio_hi=2.0, lo=-1.0, hi=1.0), cube2=v2)
+    m1 = v1.astype(np.float64).max(axis=0).ravel()
+    m2 = v2.astype(np.float64).max(axis=0).ravel()
+    pos = m1 > 0
+    assert (~pos).sum() == n * 6 and pos.sum() == n * (n - 6)
+    assert np.all(rgba[~pos] == 0.0)
+    s = np.clip((m2[pos] / m1[pos] - 0.0) / 2.0, 0.0, 1.0)
+    for ch in range(4):
+        ref = np.interp(s, np.arange(64) / 63.0, lut[:, ch].astype(np.float64))
+        assert np.max(np.abs(rgba[pos, ch] - ref)) < 1e-12
