@@ -139,7 +139,7 @@ typedef struct {
  *  mip_alpha       MIP alpha: 0 = colour-table alpha (MIP0) or s_max (MIP1, MIP_RGB);
  *                  1 = opaque; 2 = opaque where s_max exceeds the scaled min_t, s_max (MIP1,
  *                  MIP_RGB) or table alpha (MIP0) elsewhere (the transparency workaround of
- *                  Section 5.4).
+ *                  the Discussion, Section 5.7).
  *  ratio           0 = none; 1/2 = line-ratio method 1/2 of Section 4.5 (needs vol2, mode
  *                  SVR_MIP0, box_arm 0, filter none or clip); the ratio is mapped onto
  *                  [ratio_lo, ratio_hi].
@@ -205,7 +205,7 @@ svr_status svr_smooth(const svr_cube_view* in, const float* taps_host, int32_t n
 
 /* ---------------------------------------------------------------- moment maps
  * Moment maps of every spectrum of a cube over the channel window [z0, z0 + nz_w)
- * (Section 2.1, Eq. mom0 and Eq. mom1, and the argmax variant described with them).  A
+ * (Section 2.2, Eq. mom0 and Eq. mom1, and the argmax variant described with them).  A
  * channel counts when its value is finite and inside [min_t, max_t] (pass -inf / +inf for
  * no clipping).  For the spectrum at (x, y):
  *   m0_out[y][x]     = dv * sum of the counted values (dv: channel width);
@@ -252,24 +252,47 @@ svr_status svr_render_backward(const svr_volume* vol, const svr_camera* cam, con
 
 /* ---------------------------------------------------------------- batched rendering
  * Render n volumes, each with its own camera and output image, in ONE persistent launch:
- * a device work queue of (volume, 16x16 tile) items ordered by estimated cost is drained
- * by workgroups that claim items with an atomic counter.  The launch pair (counter reset,
+ * a device work queue of (volume, tile) items ordered by estimated cost is drained by
+ * workgroups that claim items with an atomic counter.  The launch pair (counter reset,
  * persistent kernel) is captured once into a HIP graph; svr_batch_launch replays it.  The
- * lut/params/volumes/outputs must stay alive and unchanged in shape until destroy.
- * tune != 0 times the candidate launch shapes on `stream` at creation and keeps the
- * fastest (the autotuner); tune == 0 uses the default shape.  Each image equals, bit for
- * bit, what svr_render gives for that volume and camera. */
+ * lut/params/volumes/outputs must stay alive and unchanged in shape until destroy.  Each
+ * image equals, bit for bit, what svr_render gives for that volume and camera.  The
+ * many detection sub-cubes of a survey (Section 1) motivate the form.
+ * tune: 0 = the default shape (the volumes' brick edge, 16 x 16 pixel tiles, 4 workgroups
+ * per CU); 1 = the autotuner's choice for the batch's size class, taken from the tuning
+ * cache when it holds one, else searched and stored; 2 = always search (and store).  The
+ * search times every combination of brick edge (8, 16) x tile (8 x 32, 16 x 16, 32 x 8
+ * pixels) x grid (2, 4, 8 workgroups per CU) as the median of three launches on `stream`
+ * (synchronising it).  When the other brick edge wins, the batch keeps library-owned
+ * copies of the volumes re-bricked to it (freed by svr_batch_destroy).  The size class is
+ * the storage type, transfer function, box smoothing on/off and the log2 buckets of n, the
+ * median voxel count and the median image size (and the CU count). */
 typedef struct svr_batch svr_batch;
 svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cams, int32_t n,
                             const svr_lut* lut, const svr_params* params,
                             float* const* rgba_outs, int32_t tune, void* stream,
                             svr_batch** out);
 svr_status svr_batch_launch(svr_batch* batch, void* stream);
-/* items = work-queue length, grid = workgroups of the persistent launch, tile_waves_x =
- * width of the 4-wave (8x8 pixels per wave) tile in waves: 1 (8x32 pixels), 2 (16x16) or
- * 4 (32x8), as chosen by the autotuner (or the default 2). */
-svr_status svr_batch_info(const svr_batch* batch, int64_t* items, int32_t* grid,
-                          int32_t* tile_waves_x);
+/* The launch the batch replays.  items = work-queue length, grid = workgroups of the
+ * persistent launch, tile_waves_x = width of the 4-wave (8 x 8 pixels per wave) tile in
+ * waves: 1 (8 x 32 pixels), 2 (16 x 16) or 4 (32 x 8); brick = brick edge of the volumes it
+ * reads; from_cache = 1 when the choice came from the tuning cache; default_ms / tuned_ms =
+ * median launch time of the default shape and of the chosen one when the batch searched
+ * (0 otherwise). */
+typedef struct {
+    int64_t items;
+    int32_t grid;
+    int32_t tile_waves_x;
+    int32_t brick;
+    int32_t from_cache;
+    float default_ms;
+    float tuned_ms;
+} svr_batch_stats;
+svr_status svr_batch_info(const svr_batch* batch, svr_batch_stats* stats);
+/* Tuning cache file (text, one line per size class, appended to): `path`, or none when
+ * path is NULL or empty.  Until this is called the environment variable SVR_TUNE_CACHE
+ * names it (none when unset).  Process-wide. */
+svr_status svr_set_tune_cache(const char* path);
 svr_status svr_batch_destroy(svr_batch* batch);
 
 /* Wait for `stream` and report any pending asynchronous HIP error. */

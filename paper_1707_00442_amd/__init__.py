@@ -303,4 +303,7 @@ def svr_sync(stream=None):
 from ._train import (  # noqa: E402,F401
     svr_render_train_workspace, svr_render_train, svr_render_backward, RenderFn,
 )
-from ._batch import Batch, svr_batch_create, svr_batch_launch, svr_batch_info, svr_batch_destroy  # noqa: E402,F401,E501
+from ._batch import (  # noqa: E402,F401
+    Batch, svr_batch_create, svr_batch_launch, svr_batch_info, svr_batch_destroy,
+    svr_set_tune_cache,
+)

@@ -9,9 +9,16 @@ import torch
 class Batch:
     """Owner of an svr_batch handle; keeps the volumes, table and outputs alive."""
 
-    def __init__(self, handle, vols, lut, outs, items, grid, tile_waves_x):
+    def __init__(self, handle, vols, lut, outs):
         self.handle, self.vols, self.lut, self.outs = handle, vols, lut, outs
-        self.items, self.grid, self.tile_waves_x = items, grid, tile_waves_x
+        self.stats = {}
+
+    def __getattr__(self, name):
+        # items, grid, tile_waves_x, brick, from_cache, default_ms, tuned_ms
+        stats = self.__dict__.get("stats", {})
+        if name in stats:
+            return stats[name]
+        raise AttributeError(name)
 
     @property
     def _as_parameter_(self):
@@ -35,7 +42,8 @@ class Batch:
             pass
 
 
-def svr_batch_create(vols, cameras, lut, params=None, outs=None, tune=False, stream=None, **kw):
+def svr_batch_create(vols, cameras, lut, params=None, outs=None, tune=0, stream=None, **kw):
+    """tune: 0 default shape, 1 (or True) tuned with the cache, 2 always search."""
     from . import _capi, lib, _check, _stream, camera_struct, params_struct, lut_struct
     n = len(vols)
     cams = (_capi.Camera * n)(*[camera_struct(c) for c in cameras])
@@ -47,10 +55,10 @@ def svr_batch_create(vols, cameras, lut, params=None, outs=None, tune=False, str
     p = params_struct(params, **kw)
     t = lut_struct(lut)
     h = C.c_void_p()
-    _check(lib().svr_batch_create(hv, cams, n, C.byref(t), C.byref(p), ho, int(bool(tune)),
+    _check(lib().svr_batch_create(hv, cams, n, C.byref(t), C.byref(p), ho, int(tune),
                                   _stream(stream), C.byref(h)), "svr_batch_create")
-    b = Batch(h.value, list(vols), lut, outs, 0, 0, 0)
-    b.items, b.grid, b.tile_waves_x = svr_batch_info(b)
+    b = Batch(h.value, list(vols), lut, outs)
+    b.stats = svr_batch_info(b)
     return b
 
 
@@ -60,10 +68,17 @@ def svr_batch_launch(batch, stream=None):
 
 
 def svr_batch_info(batch):
+    """The launch the batch replays, as a dict (fields of svr_batch_stats)."""
+    from . import lib, _check, _capi
+    st = _capi.BatchStats()
+    _check(lib().svr_batch_info(batch, C.byref(st)), "svr_batch_info")
+    return {name: getattr(st, name) for name, _ in _capi.BatchStats._fields_}
+
+
+def svr_set_tune_cache(path):
+    """Tuning cache file of the batched autotuner (None: no cache)."""
     from . import lib, _check
-    it, g, w = C.c_int64(), C.c_int32(), C.c_int32()
-    _check(lib().svr_batch_info(batch, C.byref(it), C.byref(g), C.byref(w)), "svr_batch_info")
-    return it.value, g.value, w.value
+    _check(lib().svr_set_tune_cache(path.encode() if path else None), "svr_set_tune_cache")
 
 
 def svr_batch_destroy(batch):

@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsvr.so")
+# SVR_LIBRARY may name another build of the same library (the tests load a build whose
+# host code carries AddressSanitizer); by default the in-tree libsvr.so
+LIB_PATH = os.environ.get("SVR_LIBRARY") or os.path.join(HERE, "libsvr.so")
 
 SVR_OK, SVR_EINVAL, SVR_ENOMEM, SVR_EHIP, SVR_EUNSUPPORTED = range(5)
 SVR_F32, SVR_F16, SVR_BF16 = range(3)
@@ -24,7 +26,7 @@ EXPORTS = (
     "svr_smooth",
     "svr_line_ratio", "svr_moments", "svr_render_train_workspace", "svr_render_train",
     "svr_render_backward", "svr_batch_create", "svr_batch_launch", "svr_batch_info",
-    "svr_batch_destroy", "svr_sync",
+    "svr_batch_destroy", "svr_set_tune_cache", "svr_sync",
 )
 
 
@@ -42,6 +44,12 @@ class Camera(C.Structure):
 
 class Lut(C.Structure):
     _fields_ = [("rgba", C.c_void_p), ("n", C.c_int32)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("items", C.c_int64), ("grid", C.c_int32), ("tile_waves_x", C.c_int32),
+                ("brick", C.c_int32), ("from_cache", C.c_int32), ("default_ms", C.c_float),
+                ("tuned_ms", C.c_float)]
 
 
 class Params(C.Structure):
@@ -95,8 +103,9 @@ def load():
         "svr_batch_create": (C.c_int, [P(vp), P(Camera), i32, P(Lut), P(Params), P(vp), i32,
                                        vp, P(vp)]),
         "svr_batch_launch": (C.c_int, [vp, vp]),
-        "svr_batch_info": (C.c_int, [vp, P(i64), P(i32), P(i32)]),
+        "svr_batch_info": (C.c_int, [vp, P(BatchStats)]),
         "svr_batch_destroy": (C.c_int, [vp]),
+        "svr_set_tune_cache": (C.c_int, [C.c_char_p]),
         "svr_sync": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():

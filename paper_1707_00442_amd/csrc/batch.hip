@@ -8,12 +8,24 @@
 // svr_render (so every image is bit-identical to a single-image render), and loops until
 // the queue is empty -- every workgroup exits once the counter passes the queue length.
 // The pair (counter reset kernel, persistent kernel) is captured once into a HIP graph.
-// The autotuner times tile shapes (8x32, 16x16, 32x8 pixels: four 8x8 waves) and grid
-// sizes (2, 4, 8 workgroups per CU) on the real batch and keeps the fastest.
+//
+// The autotuner searches brick edge (8, 16) x tile shape (8x32, 16x16, 32x8 pixels: four
+// 8x8 waves) x grid size (2, 4, 8 workgroups per CU) on the real batch: each candidate is
+// timed as the median of three launches after a warm-up.  A brick edge other than that of
+// the caller's volumes is tried on copies re-bricked by the library (the images do not
+// depend on the brick edge: the same corners are read), which the batch keeps when they
+// win.  The choice is stored per size class (storage type, transfer function, smoothing,
+// and the log2 buckets of the batch size, the median voxel count and the median image
+// size) in a text cache file that later batches of the same class reuse without timing.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "march.h"
@@ -181,6 +193,9 @@ using namespace svr;
 struct svr_batch {
     int n = 0;
     int mode = 0, dtype = 0, brick = 8;
+    std::vector<svr_volume*> copies;  // re-bricked copies of the volumes (library-owned)
+    int from_cache = 0;
+    float default_ms = 0.0f, tuned_ms = 0.0f;
     BatchVol* d_vols = nullptr;
     int2* d_items = nullptr;
     size_t items_cap = 0;
@@ -195,6 +210,11 @@ struct svr_batch {
     svr_lut lut{};
 };
 
+static void free_copies(std::vector<svr_volume*>& c) {
+    for (svr_volume* v : c) (void)svr_volume_destroy(v);
+    c.clear();
+}
+
 static void batch_free(svr_batch* b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -202,7 +222,95 @@ static void batch_free(svr_batch* b) {
     if (b->d_vols) (void)hipFree(b->d_vols);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_counter) (void)hipFree(b->d_counter);
+    free_copies(b->copies);
     delete b;
+}
+
+// ---------------------------------------------------------------- tuning cache
+// One line per size class: "<key> <brick> <tile_waves_x> <workgroups per CU>".
+static std::mutex g_cache_mu;
+static std::string g_cache_path;  // empty: no cache file
+static bool g_cache_set = false;  // set by svr_set_tune_cache (else SVR_TUNE_CACHE is read)
+
+static void cache_default() {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_cache_set) return;
+    const char* env = getenv("SVR_TUNE_CACHE");
+    g_cache_path = env ? env : "";
+    g_cache_set = true;
+}
+
+static int log2_bucket(double x) { return x >= 1.0 ? (int)floor(log2(x)) : 0; }
+
+static std::string size_class(const svr_batch* b, const svr_volume* const* vols, int cus) {
+    std::vector<double> vox(b->n), pix(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        vox[i] = (double)vols[i]->d.nx * vols[i]->d.ny * vols[i]->d.nz;
+        pix[i] = (double)b->vols[i].cam.width * b->vols[i].cam.height;
+    }
+    std::nth_element(vox.begin(), vox.begin() + b->n / 2, vox.end());
+    std::nth_element(pix.begin(), pix.begin() + b->n / 2, pix.end());
+    char key[160];
+    snprintf(key, sizeof key, "dtype%d_mode%d_box%d_n%d_vox%d_pix%d_cu%d", b->dtype, b->mode,
+             b->args.p.box_arm > 0 ? 1 : 0, log2_bucket(b->n), log2_bucket(vox[b->n / 2]),
+             log2_bucket(pix[b->n / 2]), cus);
+    return key;
+}
+
+static bool cache_lookup(const std::string& key, int* brick, int* tw, int* per_cu) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_cache_path.empty()) return false;
+    FILE* f = fopen(g_cache_path.c_str(), "r");
+    if (!f) return false;
+    char k[160];
+    int br, t, pc;
+    bool found = false;
+    while (fscanf(f, "%159s %d %d %d", k, &br, &t, &pc) == 4) {
+        if (key == k && (br == 8 || br == 16) && (t == 1 || t == 2 || t == 4) && pc >= 1 &&
+            pc <= 64) {  // the last entry for the key wins
+            *brick = br;
+            *tw = t;
+            *per_cu = pc;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string& key, int brick, int tw, int per_cu) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_cache_path.empty()) return;
+    FILE* f = fopen(g_cache_path.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d\n", key.c_str(), brick, tw, per_cu);
+    fclose(f);
+}
+
+// Copies of the batch's volumes with brick edge `brick`: each exported to a linear cube of
+// its storage type and uploaded again (an exact copy, same values and min/max).
+static svr_status rebrick(const svr_volume* const* vols, int n, int brick, hipStream_t s,
+                          std::vector<svr_volume*>& out) {
+    size_t most = 0;
+    for (int i = 0; i < n; ++i)
+        most = std::max(most, (size_t)vols[i]->d.nx * vols[i]->d.ny * vols[i]->d.nz *
+                                  (vols[i]->d.dtype == SVR_F32 ? 4 : 2));
+    void* lin = nullptr;
+    svr_status st = hip_fail(hipMalloc(&lin, most), "re-brick buffer");
+    for (int i = 0; i < n && !st; ++i) {
+        st = svr_volume_export(vols[i], lin, s);
+        svr_cube_view cv{lin, vols[i]->d.dtype, vols[i]->d.nx, vols[i]->d.ny, vols[i]->d.nz,
+                         0, 0, 0};
+        svr_volume* v = nullptr;
+        if (!st) st = svr_volume_create(&cv, vols[i]->d.dtype, brick, NAN, s, &v);
+        if (!st) out.push_back(v);
+    }
+    if (lin) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(lin);
+    }
+    if (st) free_copies(out);
+    return st;
 }
 
 // Build the cost-ordered queue for tile shape tw and upload it.
@@ -256,6 +364,25 @@ static svr_status batch_items(svr_batch* b, int tw, hipStream_t s) {
     return st;
 }
 
+static svr_status batch_enqueue(const svr_batch* b, int grid, hipStream_t s);
+
+// Median of three timed launches of the current queue at `grid` workgroups, after a warm-up.
+static svr_status batch_time(const svr_batch* b, int grid, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1, float* median_ms) {
+    svr_status st = batch_enqueue(b, grid, s);
+    float ms[3] = {0.0f, 0.0f, 0.0f};
+    for (int r = 0; r < 3 && !st; ++r) {
+        st = hip_fail(hipEventRecord(e0, s), "autotune event");
+        if (!st) st = batch_enqueue(b, grid, s);
+        if (!st) st = hip_fail(hipEventRecord(e1, s), "autotune event");
+        if (!st) st = hip_fail(hipEventSynchronize(e1), "autotune");
+        if (!st) st = hip_fail(hipEventElapsedTime(&ms[r], e0, e1), "autotune time");
+    }
+    std::sort(ms, ms + 3);
+    *median_ms = ms[1];
+    return st;
+}
+
 static svr_status batch_enqueue(const svr_batch* b, int grid, hipStream_t s) {
     // every table the persistent kernel reads must be in place and sized for the queue
     if (!b->args.items || !b->args.vols || !b->args.counter || !b->args.lut ||
@@ -279,6 +406,11 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
         set_error("svr_batch_create: null argument or n < 1");
         return SVR_EINVAL;
     }
+    if (tune < 0 || tune > 2) {
+        set_error("svr_batch_create: tune = %d (0, 1 or 2)", tune);
+        return SVR_EINVAL;
+    }
+    cache_default();
     svr_status st = check_lut(lut);
     if (st) return st;
     if ((st = check_params(params, vols[0]))) return st;
@@ -320,9 +452,6 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
     b->args.lut = reinterpret_cast<const float4*>(lut->rgba);
     b->args.lut_n = lut->n;
     b->args.p = *params;
-    bool wide = false;
-    for (int i = 0; i < n; ++i) wide = wide || wide_volume(vols[i]->d);
-    b->fn = batch_pick_any(b->dtype, b->brick, wide, b->mode);
     b->lds = render_lds_bytes(lut->n, params->box_arm, 0);
     hipError_t e = hipMalloc(&b->d_counter, 64);
     if (e != hipSuccess) {
@@ -334,37 +463,71 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
-    int best_tw = 2, best_grid = cus * 4;
+    // default shape: the caller's brick edge, 16 x 16 pixel tiles, 4 workgroups per CU
+    const int native = b->brick, other = native == 8 ? 16 : 8;
+    int best_brick = native, best_tw = 2, best_pc = 4;
+    std::vector<svr_volume*>& copies = b->copies;
+    auto use_brick = [&](int brick) -> svr_status {
+        bool wide = false;
+        for (int i = 0; i < n; ++i) {
+            const svr_volume* v = brick == native ? vols[i] : copies[i];
+            b->vols[i].v = v->d;
+            wide = wide || wide_volume(v->d);
+        }
+        b->fn = batch_pick_any(b->dtype, brick, wide, b->mode);
+        return SVR_OK;
+    };
     if (tune) {
-        hipEvent_t e0, e1;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        float best_ms = INFINITY;
-        const int tws[3] = {2, 4, 1};
-        const int per_cu[3] = {4, 8, 2};
-        for (int ti = 0; ti < 3 && !st; ++ti) {
-            st = batch_items(b, tws[ti], s);
-            for (int gi = 0; gi < 3 && !st; ++gi) {
-                const int grid = cus * per_cu[gi];
-                st = batch_enqueue(b, grid, s);  // warm-up
-                if (st) break;
-                (void)hipEventRecord(e0, s);
-                st = batch_enqueue(b, grid, s);
-                if (st) break;
-                (void)hipEventRecord(e1, s);
-                st = hip_fail(hipEventSynchronize(e1), "batch autotune");
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (!st && ms < best_ms) {
-                    best_ms = ms;
-                    best_tw = tws[ti];
-                    best_grid = grid;
+        const std::string key = size_class(b, vols, cus);
+        int cb = 0, ct = 0, cp = 0;
+        if (tune == 1 && cache_lookup(key, &cb, &ct, &cp)) {
+            best_brick = cb;
+            best_tw = ct;
+            best_pc = cp;
+            b->from_cache = 1;
+        } else {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            st = hip_fail(hipEventCreate(&e0), "autotune event");
+            if (!st) st = hip_fail(hipEventCreate(&e1), "autotune event");
+            float best_ms = INFINITY;
+            const int bricks[2] = {native, other};
+            const int tws[3] = {2, 4, 1};
+            const int per_cu[3] = {4, 8, 2};
+            for (int bi = 0; bi < 2 && !st; ++bi) {
+                if (bricks[bi] != native && copies.empty())
+                    st = rebrick(vols, n, bricks[bi], s, copies);
+                if (!st) st = use_brick(bricks[bi]);
+                for (int ti = 0; ti < 3 && !st; ++ti) {
+                    st = batch_items(b, tws[ti], s);
+                    for (int gi = 0; gi < 3 && !st; ++gi) {
+                        float ms = 0.0f;
+                        st = batch_time(b, cus * per_cu[gi], s, e0, e1, &ms);
+                        if (st) break;
+                        if (bi == 0 && ti == 0 && gi == 0) b->default_ms = ms;
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best_brick = bricks[bi];
+                            best_tw = tws[ti];
+                            best_pc = per_cu[gi];
+                        }
+                    }
                 }
             }
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (!st) {
+                b->tuned_ms = best_ms;
+                cache_store(key, best_brick, best_tw, best_pc);
+            }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
     }
+    // keep re-bricked copies only when their brick edge was chosen
+    if (!st && best_brick == native) free_copies(copies);
+    if (!st && best_brick != native && copies.empty())
+        st = rebrick(vols, n, best_brick, s, copies);
+    if (!st) st = use_brick(best_brick);
+    b->brick = best_brick;
+    const int best_grid = cus * best_pc;
     if (!st) st = batch_items(b, best_tw, s);
     b->grid = best_grid;
     if (!st) {
@@ -401,15 +564,25 @@ svr_status svr_batch_launch(svr_batch* batch, void* stream) {
                     "batch graph launch");
 }
 
-svr_status svr_batch_info(const svr_batch* batch, int64_t* items, int32_t* grid,
-                          int32_t* tile_waves_x) {
-    if (!batch) {
-        set_error("svr_batch_info: null batch");
+svr_status svr_batch_info(const svr_batch* batch, svr_batch_stats* stats) {
+    if (!batch || !stats) {
+        set_error("svr_batch_info: null argument");
         return SVR_EINVAL;
     }
-    if (items) *items = batch->args.nitems;
-    if (grid) *grid = batch->grid;
-    if (tile_waves_x) *tile_waves_x = batch->args.tw;
+    stats->items = batch->args.nitems;
+    stats->grid = batch->grid;
+    stats->tile_waves_x = batch->args.tw;
+    stats->brick = batch->brick;
+    stats->from_cache = batch->from_cache;
+    stats->default_ms = batch->default_ms;
+    stats->tuned_ms = batch->tuned_ms;
+    return SVR_OK;
+}
+
+svr_status svr_set_tune_cache(const char* path) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_cache_path = path ? path : "";
+    g_cache_set = true;
     return SVR_OK;
 }
 
