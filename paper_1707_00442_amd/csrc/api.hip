@@ -187,17 +187,12 @@ svr_status svr_volume_create(const svr_cube_view* src, int32_t storage, int32_t 
     if (brick == 0) brick = 8;
     SVR_CHECK(brick == 8 || brick == 16, "brick %d (8 or 16)", brick);
     SVR_CHECK(!isinf(nan_fill), "nan_fill must be finite or NaN");
-    VolDesc d;
-    d.nx = src->nx;
-    d.ny = src->ny;
-    d.nz = src->nz;
-    d.nbx = (src->nx + brick - 1) / brick;
-    d.nby = (src->ny + brick - 1) / brick;
-    d.nbz = (src->nz + brick - 1) / brick;
-    d.dtype = storage;
-    d.brick = brick;
-    const int E = brick + 1;
-    d.pitch = (uint32_t)((brick_elems(storage, brick) + 63) / 64 * 64);
+    if (src->nx > 0xffffff || src->ny > 0xffffff || src->nz > 0xffffff) {
+        set_error("svr_volume_create: dims %d x %d x %d: each must be below 2^24", src->nx,
+                  src->ny, src->nz);
+        return SVR_EUNSUPPORTED;
+    }
+    VolDesc d = make_voldesc(src->nx, src->ny, src->nz, storage, brick);
     const uint64_t nbricks = (uint64_t)d.nbx * d.nby * d.nbz;
     const uint64_t elems = nbricks * d.pitch;
     if (elems >= (1ull << 32) || nbricks >= (1ull << 24)) {
@@ -351,8 +346,8 @@ svr_status svr_line_ratio(const svr_cube_view* cube, int32_t z0_a, int32_t z0_b,
     SVR_CHECK(nz_w >= 1 && nz_w <= 65535, "svr_line_ratio: window length %d", nz_w);
     SVR_CHECK(z0_a >= 0 && z0_b >= 0 && (int64_t)z0_a + nz_w <= cube->nz &&
                   (int64_t)z0_b + nz_w <= cube->nz,
-              "svr_line_ratio: windows [%d, %d) and [%d, %d) outside 0..%d", z0_a, z0_a + nz_w,
-              z0_b, z0_b + nz_w, cube->nz);
+              "svr_line_ratio: windows [%d, %lld) and [%d, %lld) outside 0..%d", z0_a,
+              (long long)z0_a + nz_w, z0_b, (long long)z0_b + nz_w, cube->nz);
     SVR_CHECK(cube->ny <= 65535, "svr_line_ratio: ny too large for the launch grid");
     SVR_CHECK(!isnan(min_t_a) && !isnan(min_t_b) && !isnan(datamin), "svr_line_ratio: NaN argument");
     SVR_CHECK(ratio_out != nullptr, "svr_line_ratio: null output");
@@ -366,7 +361,8 @@ svr_status svr_moments(const svr_cube_view* cube, int32_t z0, int32_t nz_w, floa
     svr_status st = check_view(cube, "svr_moments");
     if (st) return st;
     SVR_CHECK(nz_w >= 1 && z0 >= 0 && (int64_t)z0 + nz_w <= cube->nz,
-              "svr_moments: window [%d, %d) outside 0..%d", z0, z0 + nz_w, cube->nz);
+              "svr_moments: window [%d, %lld) outside 0..%d", z0, (long long)z0 + nz_w,
+              cube->nz);
     SVR_CHECK(cube->ny <= 65535, "svr_moments: ny too large for the launch grid");
     SVR_CHECK(!isnan(dv) && !isnan(min_t) && !isnan(max_t), "svr_moments: NaN argument");
     SVR_CHECK(min_t <= max_t, "svr_moments: min_t %g > max_t %g", (double)min_t, (double)max_t);

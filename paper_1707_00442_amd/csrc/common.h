@@ -43,6 +43,49 @@ __host__ __device__ __forceinline__ uint32_t brick_loc(uint32_t lx, uint32_t ly,
     return DT == SVR_F32 ? (lz * E + ly) * E + lx : 2u * ((lz * C + ly) * E + lx);
 }
 
+// Element offset of voxel cell (ix, iy, iz) in bricked storage: brick index (bz * nby + by)
+// * nbx + bx times the pitch, plus the in-brick offset.  Coordinates, brick counts and the
+// pitch are below 2^24 (checked at volume creation), which lets the device use 24-bit
+// multiplies; the total is below 2^32.
+template <int DT, int C>
+__host__ __device__ __forceinline__ uint32_t cell_offset(uint32_t ix, uint32_t iy, uint32_t iz,
+                                                         uint32_t nbx, uint32_t nby,
+                                                         uint32_t pitch) {
+    constexpr int SH = C == 8 ? 3 : 4;
+    __builtin_assume(ix <= 0xffffffu);
+    __builtin_assume(iy <= 0xffffffu);
+    __builtin_assume(iz <= 0xffffffu);
+    uint32_t b = (iz >> SH) * nby + (iy >> SH);
+    __builtin_assume(b <= 0xffffffu);
+    b = b * nbx + (ix >> SH);
+    __builtin_assume(b <= 0xffffffu);
+    return b * pitch + brick_loc<DT, C>(ix & (C - 1), iy & (C - 1), iz & (C - 1));
+}
+
+// Largest element offset, from a cell's first element, that a trilinear fetch reads: the
+// corner (x + 1, y + 1, z + 1) for float32, the last element of the z + 1 pair face for
+// 16-bit storage.
+template <int DT, int C>
+__host__ __device__ constexpr uint32_t corner_span() {
+    return DT == SVR_F32 ? (uint32_t)((C + 1) * (C + 1) + (C + 1) + 1)
+                         : (uint32_t)(2 * C * (C + 1) + 3);
+}
+
+// Brick grid and pitch of a volume of nx x ny x nz voxels (data and clim left null).
+inline VolDesc make_voldesc(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, int32_t brick) {
+    VolDesc d{};
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    d.nbx = (nx + brick - 1) / brick;
+    d.nby = (ny + brick - 1) / brick;
+    d.nbz = (nz + brick - 1) / brick;
+    d.dtype = dtype;
+    d.brick = brick;
+    d.pitch = (uint32_t)((brick_elems(dtype, brick) + 63) / 64 * 64);
+    return d;
+}
+
 // Element loaders: stored type -> float32.
 template <int DT> struct Elem;
 template <> struct Elem<SVR_F32> {

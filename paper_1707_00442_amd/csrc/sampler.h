@@ -71,14 +71,7 @@ struct Sampler {
     // Element offset of voxel cell (ix, iy, iz) inside the bricked storage: brick index
     // (below 2^24) times the pitch plus the in-brick offset, below 2^32 in total.
     __device__ __forceinline__ uint32_t offset(uint32_t ix, uint32_t iy, uint32_t iz) const {
-        __builtin_assume(ix <= kM24);
-        __builtin_assume(iy <= kM24);
-        __builtin_assume(iz <= kM24);
-        uint32_t b = (iz >> SH) * nby + (iy >> SH);
-        __builtin_assume(b <= kM24);
-        b = b * nbx + (ix >> SH);
-        __builtin_assume(b <= kM24);
-        return b * pitch + brick_loc<DT, C>(ix & (C - 1), iy & (C - 1), iz & (C - 1));
+        return cell_offset<DT, C>(ix, iy, iz, nbx, nby, pitch);
     }
 
     __device__ __forceinline__ const T* at(uint32_t off) const {

@@ -215,10 +215,17 @@ __global__ __launch_bounds__(kBlock) void brick_group_kernel(const typename Elem
                 buf[j] = *reinterpret_cast<const Vec16<TI>*>(src + s_row[row] + x0 + q * VI);
             }
         }
-        // the apron column x0 + G C (clamped), one element per row
-        float ap = 0.0f;
-        if (threadIdx.x < E * E)
-            ap = Elem<DT_IN>::get(src + s_row[threadIdx.x], (uint32_t)min(x0 + G * C, dst.nx - 1));
+        // the apron column x0 + G C (clamped), one element per row: E * E rows (289 for
+        // 16-voxel bricks, more than the workgroup's lanes)
+        constexpr int NAP = (E * E + kBlock - 1) / kBlock;
+        float ap[NAP];
+#pragma unroll
+        for (int j = 0; j < NAP; ++j) {
+            const int row = threadIdx.x + j * kBlock;
+            ap[j] = row < E * E ? Elem<DT_IN>::get(src + s_row[row],
+                                                   (uint32_t)min(x0 + G * C, dst.nx - 1))
+                                : 0.0f;
+        }
 #pragma unroll
         for (int j = 0; j < NLD; ++j) {
             const int i = threadIdx.x + j * kBlock;
@@ -233,7 +240,11 @@ __global__ __launch_bounds__(kBlock) void brick_group_kernel(const typename Elem
                     *reinterpret_cast<float4*>(dstp + m) = make_float4(f[m], f[m + 1], f[m + 2], f[m + 3]);
             }
         }
-        if (threadIdx.x < E * E) tile[threadIdx.x * WP + G * C] = take(ap);
+#pragma unroll
+        for (int j = 0; j < NAP; ++j) {
+            const int row = threadIdx.x + j * kBlock;
+            if (row < E * E) tile[row * WP + G * C] = take(ap[j]);
+        }
     } else {
         constexpr int NLD = (E * E * W + kBlock - 1) / kBlock;
         float vals[NLD];
