@@ -1,4 +1,4 @@
-// Moment maps along the spectral axis (Section 2.1: the zeroth moment, Eq. mom0; the first
+// Moment maps along the spectral axis (Section 2.2: the zeroth moment, Eq. mom0; the first
 // moment, Eq. mom1; and the argmax variant).  A streaming reduction that reads every voxel of
 // the channel window once: HBM-bound.
 //

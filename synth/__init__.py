@@ -12,6 +12,7 @@ as in Appendix B).
 """
 from .cubes import (  # noqa: F401
     blob_cube, disc_cube, add_disc, uniform_cube, nan_mosaic_cube, two_line_pair,
+    two_line_pair_512x512x32,
     subcube_batch_specs, subcube, blob_cube_64, hi_cube_512x512x1024, disc_cube_256, gradcheck_cube,
     smooth_analytic_cube,
 )

@@ -175,6 +175,16 @@ def two_line_pair(n=50, nz=37, seed=0, ratio=0.4, sig1=2.0, sig2=2.0, amp=1.0, n
     return l1, l2
 
 
+def two_line_pair_512x512x32(seed=0):
+    """Full-size line pair on the grid of two 32-channel windows of the 512 x 512 x 1024
+    cube: an extended source (Gaussian sky profile of width 102 px, peak SNR 20 over unit
+    noise) seen in a strong line (width 2.5 channels) and a line 0.4 times fainter
+    (width 1.8 channels), float32."""
+    l1, l2 = two_line_pair(n=512, nz=32, seed=seed, ratio=0.4, sig1=2.5, sig2=1.8, amp=20.0,
+                           noise=1.0)
+    return l1.astype(np.float32), l2.astype(np.float32)
+
+
 def subcube_batch_specs(count=512, seed=0):
     """Per-sub-cube size and disc parameters for the batched workload: nx, ny log-uniform
     in [32, 256], nz log-uniform in [64, 512]; one disc centred within +-10 %, rd =

@@ -4,8 +4,8 @@ The 512 x 512 x 1024 float32 HI-like cube (noise + 50 rotating discs, seed 0) is
 whole at 1920 x 1080 from rotation views (dt = 0.5, clipping at minT = 3, k = 0.22); the
 oracle then renders a random sample of those pixels one by one and every sampled pixel is
 compared.  Also at full size: the six transfer functions, float16/bfloat16 storage, the
-low-density parallel view, the in-ray line ratios over the two 32-channel windows, the
-voxel-wise line-ratio pass, the three smoothing passes (sampled voxels against the direct
+low-density parallel view, the in-ray line ratios over a two-line pair of the windows'
+size, the voxel-wise line-ratio pass, the three smoothing passes (sampled voxels against the direct
 triple sum) and the batched launch of the 512 sub-cubes (sampled pixels of sampled cubes).
 """
 import numpy as np
@@ -14,7 +14,8 @@ import pytest
 import oracle
 import synth
 from oracle import quant
-from helpers import COND_TOL, TOL16, TOL32, compare_render, margins, oracle_render, to_cuda
+from helpers import (COND_TOL, TOL16, TOL32, compare_render, margins, oracle_render, report,
+                     to_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +81,7 @@ def test_full_frame_transfer_functions(svr, full, mode, view):
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit (termination re-checked "
           f"{nert}), samples {int(ns.sum())}", flush=True)
     assert err <= TOL32
-    assert frag.sum() < 0.05 * hit
+    assert frag.sum() < 0.01 * hit  # measured below 0.1%
     assert hit > NPIX // 3
 
 
@@ -110,12 +111,23 @@ def test_full_frame_half_storage(svr, full, storage, mode):
     ulp_top = 2.0 ** (np.floor(np.log2(vmax)) - (10 if storage == "f16" else 7))
     slope = float(np.abs(np.diff(lut, axis=0)).max() * (lut.shape[0] - 1))
     qbound = 0.5 * ulp_top / (hi - lo) * max(slope, 1.0)
+    ref_st, _, _ = oracle_render(oracle, deq, cam, lut, params, lo, hi, pixels=pix)
+    d_st = np.abs(got - ref_st)[~frag]
     print(f"[full {storage}/{mode}] vs stored {e1:.3e}; vs float32 cube max {d.max():.3e} "
           f"mean {d.mean():.3e} (rounding bound x slope {qbound:.3e}); fragile "
           f"{frag.sum()}", flush=True)
+    report("storage_error", config="512x512x1024 HI cube, perspective 1920x1080 view 7, "
+           "heat table, clip 3, sampled pixels", storage=storage, mode=mode, seed=0,
+           max_vs_f32=float(d.max()), mean_vs_f32=float(d.mean()), max_vs_stored=e1,
+           mean_vs_stored=float(d_st.mean()), rounding_bound=qbound, pixels=int(ok.sum()))
     assert e1 <= TOL32
     assert d.mean() <= TOL16
-    assert d.max() <= max(TOL16, 1.05 * qbound)
+    if storage == "f16":
+        assert d.max() <= TOL16
+    else:
+        # Known miss of the 2e-3 bar: bfloat16's own rounding (8 significant bits) reaches
+        # ~2.4e-3 here through the table's slope; held to that rounding bound instead.
+        assert d.max() <= max(TOL16, 1.05 * qbound)
 
 
 def test_full_sparse_parallel_view(svr, full):
@@ -137,40 +149,71 @@ def test_full_sparse_parallel_view(svr, full):
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("method", [1, 2])
-def test_full_ratio_windows(svr, full, method):
-    """In-ray line ratios over the spectral windows [400, 432) and [600, 632) of the full
-    cube (both clipped at 3), at a rotation view of the 512 x 512 x 32 windows."""
-    cube = full["cube"]
-    wa, wb = np.ascontiguousarray(cube[400:432]), np.ascontiguousarray(cube[600:632])
+@pytest.fixture(scope="module")
+def pair(svr):
+    """The 512 x 512 x 32 two-line pair (an extended source in a strong and a 0.4 times
+    fainter line, unit noise): the grid of two 32-channel windows of the full cube."""
+    print("[full] building the 512x512x32 two-line pair", flush=True)
+    wa, wb = synth.two_line_pair_512x512x32(0)
     va, vb = svr.svr_volume_create(to_cuda(wa)), svr.svr_volume_create(to_cuda(wb))
     rlo, rhi = svr.svr_volume_clim(va)
     cam = synth.rotation_views(NX, NY, 32, W, H)[5].as_f32()
-    lut = synth.lut_heat(256)
-    params = dict(mode="mip0", ratio=method, filter="clip", min_t=3.0, min_t2=3.0,
-                  ratio_lo=0.0, ratio_hi=2.0)
-    got, ns, pix = _render_sampled(svr, va, cam, lut, params, rlo, rhi, seed=50 + method,
-                                   vol2=vb)
-    err, frag, _ = compare_render(oracle, got, ns, wa, cam, lut, params, rlo, rhi, cube2=wb,
-                                  pixels=pix, margins=margins(rlo, rhi, params))
-    hit = int((ns > 0).sum())
-    print(f"[full ratio m{method}] max err {err:.3e} fragile {frag.sum()} / {hit}", flush=True)
+    yield dict(wa=wa, wb=wb, va=va, vb=vb, lo=rlo, hi=rhi, cam=cam)
     va.close()
     vb.close()
-    assert err <= TOL32
-    assert hit - frag.sum() >= NPIX // 4
+
+
+RATIO_PARAMS = dict(mode="mip0", filter="clip", min_t=3.0, min_t2=3.0, ratio_lo=0.0,
+                    ratio_hi=1.0)
+
+
+def test_full_ratio_two_line_pair(svr, pair):
+    """In-ray line ratios (Section 4.5, methods 1 and 2, both cubes clipped at 3 sigma) on
+    the 512 x 512 x 32 two-line pair at a 1920 x 1080 rotation view.  Sampled pixels
+    against the oracle; at least a tenth of the compared pixels must carry colour (rays
+    through the source), and the two methods must colour them differently."""
+    lut = synth.lut_heat(256)
+    lo, hi = pair["lo"], pair["hi"]
+    imgs = {}
+    for method in (1, 2):
+        params = dict(RATIO_PARAMS, ratio=method)
+        got, ns, pix = _render_sampled(svr, pair["va"], pair["cam"], lut, params, lo, hi,
+                                       seed=50, vol2=pair["vb"])
+        err, frag, _ = compare_render(oracle, got, ns, pair["wa"], pair["cam"], lut, params,
+                                      lo, hi, cube2=pair["wb"], pixels=pix,
+                                      margins=margins(lo, hi, params), cond_tol=COND_TOL)
+        hit = int((ns > 0).sum())
+        coloured = (np.abs(got).sum(axis=1) > 0) & ~frag
+        print(f"[full ratio m{method}] max err {err:.3e} fragile {frag.sum()} / {hit} hit "
+              f"({frag.sum() / hit:.3f}), {int(coloured.sum())} compared pixels with colour",
+              flush=True)
+        assert err <= TOL32
+        assert frag.sum() <= 0.03 * hit  # measured 0.7-1.2% with the oracle's flags
+        assert coloured.sum() >= len(pix) // 10
+        imgs[method] = (got, coloured)
+    both = imgs[1][1] & imgs[2][1]
+    assert np.abs(imgs[1][0][both] - imgs[2][0][both]).max() > 1e-2
 
 
 def test_full_line_ratio_pass(svr, full):
-    """The voxel-wise ratio cube of the two windows, clipped at 3, DATAMIN = lo: every
-    voxel within one float32 rounding of the FP64 ratio."""
-    out = svr.svr_line_ratio(full["t"], 400, 600, 32, min_t_a=3.0, min_t_b=3.0,
-                             datamin=full["lo"])
+    """The voxel-wise ratio cube of the windows [400, 432) and [600, 632), unclipped,
+    DATAMIN = lo: every voxel within one float32 rounding of the FP64 ratio, and most
+    voxels carry a ratio (denominator > 0), not DATAMIN."""
+    lo = full["lo"]
+    out = svr.svr_line_ratio(full["t"], 400, 600, 32, datamin=lo)
     got = out.cpu().numpy().astype(np.float64)
-    ref = oracle.line_ratio(full["cube"], 400, 600, 32, 3.0, 3.0, datamin=full["lo"])
+    ref = oracle.line_ratio(full["cube"], 400, 600, 32, -np.inf, -np.inf, datamin=lo)
     rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
-    print(f"[full line ratio] max rel err {rel.max():.3e}", flush=True)
+    ratios = float(np.mean(ref != np.float64(np.float32(lo))))
+    print(f"[full line ratio] max rel err {rel.max():.3e}; {ratios:.3f} of the voxels carry "
+          f"a ratio", flush=True)
     assert rel.max() <= 2.0 ** -24 * 1.01
+    assert ratios > 0.4
+    # clipped at 3 on both windows: a ratio only where both lines are bright
+    out = svr.svr_line_ratio(full["t"], 400, 600, 32, min_t_a=3.0, min_t_b=3.0, datamin=lo)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.line_ratio(full["cube"], 400, 600, 32, 3.0, 3.0, datamin=lo)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * 1.01 * np.abs(ref))
 
 
 @pytest.mark.parametrize("sigma", [1, 2, 3])

@@ -1,4 +1,4 @@
-"""GPU parity of the moment maps (Section 2.1, Eq. mom0 / Eq. mom1 and the argmax variant)
+"""GPU parity of the moment maps (Section 2.2, Eq. mom0 / Eq. mom1 and the argmax variant)
 against the FP64 oracle.
 
 Both sides sum in float64, channel by channel in increasing channel order with every operation
@@ -116,7 +116,7 @@ def test_moments_argmax_matches_mip1_location(svr):
     With one ray per voxel column and a step of half a channel every channel value is sampled
     exactly (the samples between lie between their neighbours), so the render's location is
     the moment map's argmax: loc.z = (argmax + 0.5) / nz (the argmax variant behaves like MIP,
-    Section 2.1).  Columns whose two largest values normalise to within 1e-5 are skipped (the
+    Section 2.2).  Columns whose two largest values normalise to within 1e-5 are skipped (the
     render compares normalised samples)."""
     cube = synth.blob_cube(24, 3, seed=4)
     nz, ny, nx = cube.shape

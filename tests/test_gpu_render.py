@@ -14,7 +14,7 @@ import pytest
 import oracle
 import synth
 from oracle import quant
-from helpers import (AMP_MAX, COND_TOL, TOL16, TOL32, assert_counts, compare_render, f32,  # noqa: F401,E501
+from helpers import (COND_TOL, TOL16, TOL32, assert_counts, compare_render, f32, report,  # noqa: F401,E501
                      gpu_render, margins, max_err, oracle_render, to_cuda)
 
 pytestmark = pytest.mark.gpu
@@ -90,8 +90,10 @@ def test_all_modes_filters_box(svr, ragged, mode, filt, box):
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit (termination re-checked "
           f"{nert})", flush=True)
     assert err <= TOL32
-    # domain scaling maps a narrow band onto [0, 1]: more pixels amplify sample errors
-    assert frag.sum() < (0.25 if filt == "scale" else 0.05) * hit
+    # measured with the oracle's flags: at most 0.2% of the hit pixels without a filter or
+    # with clipping, up to 5% with domain scaling (a 7.5-wide band mapped onto [0, 1]
+    # stretches the rounding of the accumulated AVIP samples)
+    assert frag.sum() < (0.075 if filt == "scale" else 0.01) * hit
     assert hit > 2000
 
 
@@ -118,7 +120,7 @@ def test_star_gaussian_in_ray(svr, ragged, mode, filt):
     hit = int((ns > 0).sum())
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
     assert err <= TOL32
-    assert frag.sum() < 0.05 * hit and hit > 2000
+    assert frag.sum() < 0.01 * hit and hit > 2000  # measured below 0.5%
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
@@ -173,7 +175,7 @@ def test_frame_rate_protocol_configuration(svr, mode, box):
     hit = int((ns > 0).sum())
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
     assert err <= TOL32
-    assert frag.sum() < 0.05 * hit and hit > 5000
+    assert frag.sum() < 0.01 * hit and hit > 5000  # measured below 0.5%
 
 
 @pytest.mark.parametrize("mode", ["mip0", "mip1", "miprgb"])
@@ -216,6 +218,37 @@ def test_brick16_equals_brick8(svr, ragged, storage):
         assert torch_equal(ia, ib), mode
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("src_dtype", ["f32", "f16"])
+@pytest.mark.parametrize("dims", [(40, 30, 74), (60, 29, 56), (64, 40, 33), (32, 33, 20)])
+def test_brick16_vector_upload_apron(svr, storage, src_dtype, dims):
+    """Rows whose x extent is a multiple of the 16-byte load take the upload's vector path;
+    with 16-voxel bricks a group's x-apron column spans 17 x 17 rows, more than the
+    workgroup's 256 lanes (every row must be staged).  Renders from 16-voxel bricks equal
+    those from 8-voxel bricks, for float32 and float16 sources, in every transfer function
+    (regression: rows 256..288 of the apron column were left unstaged)."""
+    import torch
+    nx, ny, nz = dims
+    cube = synth.disc_cube(nx, ny, nz, 1, seed=nx + nz, dv_chan=8.0, centre_margin=8.0,
+                           rd_range=(2.0, 4.0), zsys_margin=10.0)
+    src = to_cuda(cube)
+    if src_dtype == "f16":
+        src = src.half()
+    lut = to_cuda(synth.lut_heat(256))
+    a = svr.svr_volume_create(src, storage=storage, brick=8)
+    b = svr.svr_volume_create(src, storage=storage, brick=16)
+    assert torch.equal(svr.svr_volume_export(a), svr.svr_volume_export(b))
+    for az in (0.0, 75.0, 160.0, 250.0):
+        cam = synth.perspective_lookat(nx, ny, nz, az, 25.0, 2.2 * max(dims), 40.0, 64,
+                                       48).as_f32()
+        for mode in MODES:
+            ia = svr.svr_render(a, cam, lut, mode=mode)
+            ib = svr.svr_render(b, cam, lut, mode=mode)
+            assert torch_equal(ia, ib), (mode, az)
+    a.close()
+    b.close()
+
+
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a, b))
@@ -239,6 +272,7 @@ def test_half_storage_blob64(svr, storage, seed, mode):
     got, ns = gpu_render(svr, vol, cam, to_cuda(lut), params, lo, hi)
     e1, frag, _ = compare_render(oracle, got, ns, deq, cam, lut, params, lo, hi,
                                  margins=margins(lo, hi, params))
+    ref_stored, _, _ = oracle_render(oracle, deq, cam, lut, params, lo, hi)
     # against the float32 cube: the storage error dominates
     vmax = float(np.abs(cube).max())
     # (no exclusions: with no filter the only discrete decision is the termination index,
@@ -254,11 +288,18 @@ def test_half_storage_blob64(svr, storage, seed, mode):
     print(f"[{storage}/{mode}/seed{seed}] vs stored {e1:.3e}  vs float32 cube max {e2:.3e} "
           f"mean {mean2:.3e} (storage rounding bound {qbound:.3e}) fragile "
           f"{frag.sum()}/{(~ok).sum()}", flush=True)
+    d1 = np.abs(got - ref_stored)[~frag]
+    report("storage_error", config="64^3 blob cube, parallel +z 256x256, ramp table",
+           storage=storage, mode=mode, seed=seed, max_vs_f32=e2, mean_vs_f32=mean2,
+           max_vs_stored=e1, mean_vs_stored=float(d1.mean()),
+           rounding_bound=qbound, pixels=int(ok.sum()))
     assert e1 <= TOL32
     if storage == "f16":
         assert e2 <= TOL16
     else:
-        # bfloat16 keeps 8 significant bits: its rounding alone can exceed 2e-3
+        # Known miss of the 2e-3 bar: bfloat16 keeps 8 significant bits, so its rounding
+        # alone (half an ulp of the largest value, mapped through the table) can exceed
+        # 2e-3; the image error is held to that rounding bound, the mean to 2e-3.
         assert e2 <= max(TOL16, 1.05 * qbound) and mean2 <= TOL16
 
 
@@ -318,7 +359,7 @@ def test_half_storage_box(svr, ragged, storage, mode):
     hit = int((ns > 0).sum())
     print(f"  max err {err:.3e} fragile {frag.sum()} / {hit} hit", flush=True)
     assert err <= TOL32
-    assert frag.sum() < 0.05 * hit and hit > 2000
+    assert frag.sum() < 0.01 * hit and hit > 2000  # measured below 0.5%
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
@@ -449,15 +490,21 @@ def test_ratio_methods(svr, method, clip):
         cam = cam.as_f32()
         got, ns = gpu_render(svr, v1, cam, to_cuda(lut), p, lo, hi, vol2=v2)
         err, frag, _ = compare_render(oracle, got, ns, l1, cam, lut, p, lo, hi, cube2=l2,
-                                      margins=margins(lo, hi, p))
+                                      margins=margins(lo, hi, p), cond_tol=COND_TOL)
         hit = int((ns > 0).sum())
-        print(f"[ratio m{method} clip={clip}] err {err:.3e} fragile {frag.sum()}/{hit}",
-              flush=True)
+        coloured = int(((np.abs(got).sum(axis=1) > 0) & ~frag).sum())
+        print(f"[ratio m{method} clip={clip}] err {err:.3e} fragile {frag.sum()}/{hit} "
+              f"({frag.sum() / hit:.3f}), {coloured} compared pixels with colour", flush=True)
         assert err <= TOL32
-        # a ratio amplifies sample errors by (range / denominator): noise-only rays divide
-        # noise by noise, clipped rays divide by values near the threshold -- many pixels
-        # are ill-conditioned by nature; the well-conditioned ones must be plentiful
-        assert hit - frag.sum() >= 400
+        # A ratio amplifies sample errors by 1/denominator.  Unclipped, method 1 divides
+        # the maxima of noise-only rays (about half the pixels are ill-conditioned by
+        # nature, and held to COND_TOL); clipped (denominator >= minT) or per sample
+        # (method 2) up to 8% are (measured 0.4-6%).
+        if method == 1 and not clip:
+            assert hit - frag.sum() >= 0.4 * hit
+        else:
+            assert frag.sum() <= 0.08 * hit
+        assert coloured >= 0.1 * hit
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
