@@ -10,7 +10,9 @@ view 40 deg), dt = 0.5 voxel:
   * the six transfer functions (MIP0, MIP1, MIP_RGB, AVIP0, AVIP1, AVIP_RGB; k = 0.22,
     clipping at minT = 3 sigma);
   * the voxel-wise line ratio of the spectral windows [400, 432) and [600, 632), and the
-    two in-ray line-ratio methods over those windows.
+    two in-ray line-ratio methods over a 512 x 512 x 32 two-line pair (the windows' grid:
+    an extended source in a strong and a 0.4 times fainter line, unit noise, both clipped at
+    3 sigma).
 value = ray samples processed per second over the whole step (samples counted per pixel
 by the renderer itself, verified against the oracle in the tests).
 
@@ -173,9 +175,13 @@ def main():
     views = [v.as_f32() for v in synth.rotation_views(nx, ny, nz, W, H)]
     lut = torch.from_numpy(synth.lut_heat(256)).cuda()
     vol = svr.svr_volume_create(cube, storage="f32")
-    win_a, win_b = cube[400:432], cube[600:632]
-    vol_a = svr.svr_volume_create(win_a.contiguous())
-    vol_b = svr.svr_volume_create(win_b.contiguous())
+    # in-ray line ratios: a two-line pair on the grid of two 32-channel windows (an extended
+    # source in a strong and a 0.4 times fainter line); the voxel-wise pass runs on the
+    # windows [400, 432) and [600, 632) of the cube itself
+    pair_a, pair_b = synth.two_line_pair_512x512x32(0)
+    vol_a = svr.svr_volume_create(torch.from_numpy(pair_a).cuda())
+    vol_b = svr.svr_volume_create(torch.from_numpy(pair_b).cuda())
+    del pair_a, pair_b
     ratio_views = [v.as_f32() for v in synth.rotation_views(nx, ny, 32, W, H)]
     taps = {s: tapgen.gauss(float(s)).astype(np.float32) for s in (1, 2, 3)}
     smooth_out = torch.empty_like(cube)
@@ -188,7 +194,7 @@ def main():
               for m in MODES}
     rlo, rhi = svr.svr_volume_clim(vol_a)
     rparams = {r: dict(mode="mip0", ratio=r, filter="clip", min_t=3.0, min_t2=3.0,
-                       clim_lo=rlo, clim_hi=rhi, ratio_lo=0.0, ratio_hi=2.0) for r in (1, 2)}
+                       clim_lo=rlo, clim_hi=rhi, ratio_lo=0.0, ratio_hi=1.0) for r in (1, 2)}
 
     K, Wu = args.steps, args.warmup
     if args.profile:
@@ -225,8 +231,7 @@ def main():
             with span(f"render_{m}"):
                 svr.svr_render(vol, cam, lut, params[m], out=imgs[m])
         with span("line_ratio"):
-            svr.svr_line_ratio(cube, 400, 600, 32, min_t_a=3.0, min_t_b=3.0, datamin=lo,
-                               out=ratio_out)
+            svr.svr_line_ratio(cube, 400, 600, 32, datamin=lo, out=ratio_out)
         rc = ratio_views[i % len(ratio_views)]
         for r in (1, 2):
             with span(f"render_ratio{r}"):
@@ -295,8 +300,9 @@ def main():
         "config": {"workload": "HI-like cube 512x512x1024 float32 (noise + 50 discs, seed 0); "
                                "perspective 1920x1080 rotation views, dt 0.5; per step: "
                                "smooth sigma 1,2,3 + upload + 6 transfer functions (clip "
-                               "minT 3) + line ratio windows [400,432)/[600,632) (pass and "
-                               "two in-ray methods)",
+                               "minT 3) + voxel-wise line ratio of windows [400,432)/"
+                               "[600,632) + the two in-ray ratio methods on a 512x512x32 "
+                               "two-line pair (clip 3 sigma)",
                    "image": [W, H], "cube": [nx, ny, nz], "dt": 0.5},
         "fps_render": frames / (sum(sum(timer.ms(f"render_{m}")) for m in MODES) * 1e-3),
         "render_samples_per_s": render_samples / (sum(sum(timer.ms(f"render_{m}"))
@@ -304,6 +310,11 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    # pixels the in-ray ratio methods coloured in the last timed step (rays through the
+    # source of the line pair), and voxels of the ratio pass that carry a ratio
+    out["ratio_coloured_pixels"] = {f"method{r}": int((rimg[r].abs().sum(dim=2) > 0).sum())
+                                    for r in (1, 2)}
+    out["line_ratio_voxels_with_ratio"] = int((ratio_out != lo).sum().item())
     log(f"main: {value:.4g} samples/s, {ms_per_step:.2f} ms/step, dominant {dominant}")
 
     if not args.no_forms:
@@ -399,7 +410,7 @@ def profile_one(args, torch, svr, synth, cube, vol, views, lut, params, taps, sm
     elif name == "upload":
         fn = lambda: svr.svr_volume_upload(vol, cube)  # noqa: E731
     elif name == "line_ratio":
-        fn = lambda: svr.svr_line_ratio(cube, 400, 600, 32, 3.0, 3.0, lo, out=ratio_out)  # noqa: E731,E501
+        fn = lambda: svr.svr_line_ratio(cube, 400, 600, 32, datamin=lo, out=ratio_out)  # noqa: E731
     elif name == "moments":
         mom = svr.svr_moments(cube)
         fn = lambda: svr.svr_moments(cube, out=mom)  # noqa: E731
@@ -460,6 +471,39 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
         ms = _time(torch, lambda: svr.svr_render(vol32, cam, lut, params[m]), 5)
         plain[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fps=1e3 / ms)
     forms["fp32_plain"] = plain
+    # the paper's Section 6 protocol on this workload: every frame of the full rotation (36
+    # views, 10 degree steps) timed on its own, fps = 1000 / median frame time
+    log("form: rotation median")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    img = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+    rot = {}
+    for m in MODES:
+        ms = []
+        for v in views:
+            ev0.record()
+            svr.svr_render(vol32, v, lut, params[m], out=img)
+            ev1.record()
+            ev1.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        rot[m] = dict(fps_median=1e3 / float(np.median(ms)), ms_min=float(np.min(ms)),
+                      ms_max=float(np.max(ms)), views=len(ms))
+    forms["rotation_36_views"] = rot
+    # the voxel-wise line-ratio pass: one 32-channel window pair is ~12 us of HBM time, so
+    # it is also timed over the 32 window offsets back to back and on 256-channel windows
+    nx_, ny_ = cube.shape[2], cube.shape[1]
+    rout = torch.empty((256, ny_, nx_), dtype=torch.float32, device="cuda")
+
+    def offsets():
+        for j in range(32):
+            svr.svr_line_ratio(cube, 400 + j, 600 + j, 32, datamin=lo, out=rout[:32])
+    ms32 = _time(torch, offsets, 5) / 32
+    ms256 = _time(torch, lambda: svr.svr_line_ratio(cube, 0, 512, 256, datamin=lo, out=rout), 5)
+    b32, b256 = 12 * 32 * nx_ * ny_, 12 * 256 * nx_ * ny_
+    forms["line_ratio_pass"] = dict(
+        offsets32_ms_per_launch=ms32, offsets32_gbps=b32 / (ms32 * 1e-3) / 1e9,
+        window256_ms=ms256, window256_gbps=b256 / (ms256 * 1e-3) / 1e9,
+        window256_hbm_frac=b256 / (ms256 * 1e-3) / PEAK_HBM)
+    del rout
     # low sample density: HBM-bound ray-march
     c = sparse_camera(synth)
     p = dict(params["mip0"], dt=1.0)
@@ -497,11 +541,23 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
         v = svr.svr_volume_create(cube, storage=st)
         r = {}
         for m in ("mip0", "avip0"):
-            _, ns = svr.svr_render(v, cam, lut, params[m], samples=True)
+            i16, ns = svr.svr_render(v, cam, lut, params[m], samples=True)
             n = int(ns.sum().item())
             ms = _time(torch, lambda: svr.svr_render(v, cam, lut, params[m]), 5)
+            # the image against the float32-storage image of the same view (the storage
+            # rounding carried through the transfer function; the error against the FP64
+            # oracle is measured in the tests)
+            # (max over the image is set by samples within the storage rounding of the
+            # clipping threshold, which flip between clipped and kept: the tests exclude
+            # such pixels; the 99.99th percentile and the count above 2e-3 show the rest)
+            i32 = svr.svr_render(vol32, cam, lut, params[m])
+            d = (i16 - i32).abs().amax(dim=2).flatten()
             r[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fps=1e3 / ms,
-                        speedup_vs_fp32=plain[m]["ms"] / ms)
+                        speedup_vs_fp32=plain[m]["ms"] / ms,
+                        max_abs_vs_fp32_storage=float(d.max()),
+                        p9999_abs_vs_fp32_storage=float(torch.quantile(d[::4].float(), 0.9999)),
+                        pixels_above_2e3=int((d > 2e-3).sum()),
+                        mean_abs_vs_fp32_storage=float(d.mean()))
         forms[f"{st}_storage"] = r
         v.close()
     vol32.close()
@@ -549,6 +605,15 @@ def _make_sub(spec):
     return synth.subcube(spec)
 
 
+def _subcube_camera(synth, sp):
+    """The sub-cube's own perspective camera: along its random view direction, at twice its
+    bounding radius, 30 degree field of view, 512 x 512."""
+    v = sp["view"] / np.linalg.norm(sp["view"])
+    radius = 0.5 * math.sqrt(sp["nx"] ** 2 + sp["ny"] ** 2 + sp["nz"] ** 2)
+    centre = ((sp["nx"] - 1) / 2, (sp["ny"] - 1) / 2, (sp["nz"] - 1) / 2)
+    return synth.perspective_direction(centre, v, 2 * radius, 30.0, 512, 512).as_f32()
+
+
 def run_batched(torch, svr, synth, lut):
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
@@ -563,63 +628,128 @@ def run_batched(torch, svr, synth, lut):
     for sp, c in zip(specs, cubes):
         tc = torch.from_numpy(c).cuda()
         vols.append(svr.svr_volume_create(tc, storage="f16"))
-        v = sp["view"] / np.linalg.norm(sp["view"])
-        radius = 0.5 * math.sqrt(sp["nx"] ** 2 + sp["ny"] ** 2 + sp["nz"] ** 2)
-        centre = ((sp["nx"] - 1) / 2, (sp["ny"] - 1) / 2, (sp["nz"] - 1) / 2)
-        cams.append(synth.perspective_direction(centre, v, 2 * radius, 30.0, 512, 512).as_f32())
+        cams.append(_subcube_camera(synth, sp))
     del cubes
     res = {}
     for m in ("mip0", "avip0"):
         p = dict(mode=m, k=0.22)
-        b = svr.svr_batch_create(vols, cams, lut, p, tune=True)
+        # the autotuner's search (brick edge x tile x grid, median of three launches each)
+        t = time.perf_counter()
+        b = svr.svr_batch_create(vols, cams, lut, p, tune=2)
+        tune_s = time.perf_counter() - t
+        d = svr.svr_batch_create(vols, cams, lut, p, tune=0, outs=b.outs)
         n = 0
         for v, c in zip(vols, cams):
             _, ns = svr.svr_render(v, c, lut, p, samples=True)
             n += int(ns.sum().item())
-        ms_b = _time(torch, lambda: b.launch(), 3)
+        ms_b = _time(torch, lambda: b.launch(), 5)
+        ms_d = _time(torch, lambda: d.launch(), 5)
         outs = b.outs
 
         def per_cube():
             for v, c, o in zip(vols, cams, outs):
                 svr.svr_render(v, c, lut, p, out=o)
         ms_p = _time(torch, per_cube, 3)
-        res[m] = dict(samples=n, batched_ms=ms_b, per_cube_launches_ms=ms_p,
+        st = b.stats
+        res[m] = dict(samples=n, batched_ms=ms_b, default_shape_ms=ms_d,
+                      tuned_vs_default=ms_d / ms_b, per_cube_launches_ms=ms_p,
                       speedup=ms_p / ms_b, samples_per_s=n / (ms_b * 1e-3),
-                      items=b.items, grid=b.grid, tile_waves_x=b.tile_waves_x)
+                      items=st["items"], grid=st["grid"], tile_waves_x=st["tile_waves_x"],
+                      brick=st["brick"], search_default_ms=st["default_ms"],
+                      search_tuned_ms=st["tuned_ms"], search_s=tune_s)
         b.close()
+        d.close()
     for v in vols:
         v.close()
     return res
 
 
+def _oracle_rate(oracle, cube64, cam, lut, p, budget, rng, threads, npx=256):
+    """Oracle samples/s on random pixels of one frame, the pixel count grown until the
+    render takes about `budget` seconds."""
+    total = cam.width * cam.height
+    while True:
+        pix = rng.choice(total, min(npx, total), replace=False)
+        t = time.perf_counter()
+        _, _, ns = oracle.render(cube64, cam, lut, p, pixels=pix, nthreads=threads)
+        dt = time.perf_counter() - t
+        if dt > 0.5 * budget or npx >= total:
+            return int(ns.sum()), dt, len(pix)
+        npx = int(min(total, npx * max(2.0, 0.8 * budget / max(dt, 1e-3))))
+
+
 def cpu_baseline(cube_np, cam, synth, lo, hi, args):
-    """The FP64 oracle on a bounded sample of pixels of the same frame (MIP0 and AVIP0)."""
+    """The FP64 oracle (test infrastructure, timed here as the CPU baseline) on bounded
+    samples: random pixels of the benchmark frame (MIP0 and AVIP0) on all host cores and on
+    one core, and short timings of the other workloads (64^3 frames, the differentiable
+    256^3 form with its FP64 adjoint, sampled pixels of sub-cubes of the batched form)."""
     import oracle
     log("CPU baseline: oracle on sampled pixels")
     cube64 = cube_np.astype(np.float64)
     lut = synth.lut_heat(256)
     threads = os.cpu_count() or 1
     rng = np.random.default_rng(0)
-    total_s, total_n, total_px = 0.0, 0, 0
     budget = args.cpu_seconds
+    total_s, total_n, total_px = 0.0, 0, 0
+    one_s, one_n = 0.0, 0
     for m in ("mip0", "avip0"):
         p = dict(mode=m, k=0.22, filter="clip", min_t=3.0, lo=lo, hi=hi)
-        npx = 512
-        while True:
-            pix = rng.choice(cam.width * cam.height, npx, replace=False)
-            t = time.perf_counter()
-            _, _, ns = oracle.render(cube64, cam, lut, p, pixels=pix, nthreads=threads)
-            dt = time.perf_counter() - t
-            if dt > 0.25 * budget or npx >= cam.width * cam.height:
-                break
-            npx = int(min(cam.width * cam.height, npx * max(2.0, 0.4 * budget / max(dt, 1e-3))))
-        total_s += dt
-        total_n += int(ns.sum())
-        total_px += npx
-    return {"value": total_n / total_s, "unit": "samples/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{total_px} random pixels of the 1920x1080 frame (MIP0 and AVIP0, clip "
-                      f"minT 3) on the 512x512x1024 cube, {total_n} samples in {total_s:.1f}s"}
+        n, dt, npx = _oracle_rate(oracle, cube64, cam, lut, p, 0.5 * budget, rng, threads)
+        total_s, total_n, total_px = total_s + dt, total_n + n, total_px + npx
+        n, dt, _ = _oracle_rate(oracle, cube64, cam, lut, p, 0.1 * budget, rng, 1, npx=16)
+        one_s, one_n = one_s + dt, one_n + n
+    del cube64
+    out = {"value": total_n / total_s, "unit": "samples/s", "cores": threads, "kind": "oracle",
+           "sample": f"{total_px} random pixels of the 1920x1080 frame (MIP0 and AVIP0, clip "
+                     f"minT 3) on the 512x512x1024 cube, {total_n} samples in {total_s:.1f}s",
+           "one_core": {"value": one_n / one_s, "unit": "samples/s", "cores": 1,
+                        "sample": f"{one_n} samples of the same frame in {one_s:.1f}s"}}
+    log("CPU baseline: other workloads")
+    cfg = {}
+    # 64^3 blob cube, full 256x256 frames
+    c0 = synth.blob_cube_64(0).astype(np.float64)
+    l0, h0 = float(c0.min()), float(c0.max())
+    cam0 = synth.ortho_axis(64, 64, 64, 256, 256, "+z").as_f32()
+    for m in ("mip0", "avip0"):
+        t = time.perf_counter()
+        _, _, ns = oracle.render(c0, cam0, synth.lut_ramp(256), dict(mode=m, k=0.22, lo=l0, hi=h0),
+                                 nthreads=threads)
+        dt = time.perf_counter() - t
+        cfg[f"blob64_{m}_256x256"] = dict(s_per_frame=dt, samples_per_s=int(ns.sum()) / dt)
+    # 256^3 differentiable form at 1024x1024: forward on all cores, FP64 adjoint on one core
+    c4 = synth.disc_cube_256(0).astype(np.float64)
+    l4, h4 = float(c4.min()), float(c4.max())
+    cam4 = synth.perspective_lookat(256, 256, 256, 30.0, 20.0, 256 * 3 ** 0.5, 40.0,
+                                    1024, 1024).as_f32()
+    tf = synth.tf_ramp(64)
+    p4 = dict(mode="avip0", opacity_from_lut=1, k=0.22, lo=l4, hi=h4)
+    n, dt, npx = _oracle_rate(oracle, c4, cam4, tf, p4, 2.0, rng, threads)
+    cfg["disc256_avip0_1024x1024_forward"] = dict(samples_per_s=n / dt, sample=f"{npx} pixels")
+    pix = rng.choice(1024 * 1024, 400, replace=False)
+    t = time.perf_counter()
+    oracle.render_grad(c4, cam4, tf, p4, np.ones((400, 4)), pixels=pix)
+    dt = time.perf_counter() - t
+    _, _, ns = oracle.render(c4, cam4, tf, p4, pixels=pix, nthreads=threads)
+    cfg["disc256_avip0_1024x1024_forward_adjoint_1core"] = dict(
+        samples_per_s=int(ns.sum()) / dt, sample="400 pixels, forward + FP64 adjoint")
+    del c4
+    # sub-cubes of the batched form (float16 values), sampled pixels of 8 of them
+    specs = synth.subcube_batch_specs(512, 0)[:8]
+    n_all, s_all = 0, 0.0
+    for sp in specs:
+        c = synth.subcube(sp).astype(np.float64)
+        camc = _subcube_camera(synth, sp)
+        pix = rng.choice(512 * 512, 2000, replace=False)
+        t = time.perf_counter()
+        _, _, ns = oracle.render(c, camc, lut, dict(mode="mip0", lo=float(c.min()),
+                                                    hi=float(c.max())),
+                                 pixels=pix, nthreads=threads)
+        s_all += time.perf_counter() - t
+        n_all += int(ns.sum())
+    cfg["subcubes_mip0_512x512"] = dict(samples_per_s=n_all / s_all,
+                                        sample="2000 pixels of each of 8 sub-cubes")
+    out["configs"] = cfg
+    return out
 
 
 if __name__ == "__main__":
