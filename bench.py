@@ -95,6 +95,11 @@ def parse():
                     help="instead of the step: the paper's frame-rate protocol (uniform [0,1] "
                          "cubes 128^3..1024^3, raw and box 3..11, MIP0 and AVIP0, median fps "
                          "over a full rotation x3 at 1000x1000, and the canvas sweep)")
+    ap.add_argument("--summarize", default=None, metavar="DIR",
+                    help="summarise rocprofv3 output written under DIR (trace/ from a "
+                         "--kernel-trace --stats run of the step, pmc_<kernel>_<COUNTER>/ from "
+                         "--pmc runs of --profile <kernel>) into markdown on stdout and "
+                         "profiles/traffic.json; no GPU needed")
     ap.add_argument("--profile", default=None,
                     help="run only this kernel on the main workload, --steps times (for "
                          "rocprofv3): render_<mode>, render_sparse, smooth_sigma<s>, upload, "
@@ -149,8 +154,96 @@ def load_traffic(kernel):
     return None
 
 
+# kernels each --profile mode launches per call (rocprofv3 kernel-name prefixes)
+PROFILE_KERNELS = {
+    "render": ("svr::render_kernel<",),
+    "smooth": ("svr::smooth_fused_kernel<",),
+    "upload": ("svr::upload_init", "svr::brick_group_kernel<", "svr::upload_final<",
+               "svr::upload_fill<"),
+    "moments": ("svr::moments_kernel<",),
+    "line_ratio": ("svr::line_ratio_kernel<",),
+    "copy": ("__amd_rocclr_copyBuffer",),
+}
+
+
+def _kernel_name(name):
+    """A rocprofv3 kernel name without 'void ' and its argument list."""
+    name = name[5:] if name.startswith("void ") else name
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def _per_call(path, kernel, calls):
+    """Counter value per call of `kernel` (KiB): the last `calls` dispatches of each of the
+    kernels that call launches, summed over those kernels, averaged over the calls."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    total = 0.0
+    for prefix in PROFILE_KERNELS[kernel_family(kernel)]:
+        vals = [float(r["Counter_Value"]) for r in rows
+                if _kernel_name(r["Kernel_Name"]).startswith(prefix)]
+        if len(vals) < calls:
+            raise SystemExit(f"{path}: {len(vals)} dispatches of {prefix}, expected {calls}")
+        total += sum(vals[-calls:])
+    return total / calls
+
+
+def summarize(d, calls=20):
+    """Markdown tables from rocprofv3 output under d, and profiles/traffic.json: HBM bytes per
+    launch = FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
+    counter reads for a 1 GiB device copy (bytes read and written are known)."""
+    import csv
+    import glob
+    out = []
+    stats = glob.glob(os.path.join(d, "trace", "*_kernel_stats.csv"))
+    if stats:
+        rows = list(csv.DictReader(open(stats[0])))
+        out.append("| kernel | calls | average (ms) | min (ms) | max (ms) | share |")
+        out.append("|---|---|---|---|---|---|")
+        for r in rows:
+            if not r["Name"].startswith("void svr::") and "svr::" not in r["Name"]:
+                continue
+            out.append(f"| `{_kernel_name(r['Name'])}` | {r['Calls']} | "
+                       f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['MinNs']) / 1e6:.4f} | "
+                       f"{float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f}% |")
+        out.append("")
+    pmc = {}
+    for path in glob.glob(os.path.join(d, "pmc_*_*_SIZE", "*counter_collection.csv")):
+        tag = os.path.basename(os.path.dirname(path))[4:]
+        kernel, counter = tag.rsplit("_", 2)[0], "_".join(tag.rsplit("_", 2)[1:])
+        pmc.setdefault(kernel, {})[counter] = _per_call(path, kernel, calls)
+    if pmc:
+        copy = pmc.pop("copy")
+        f_fetch = 2.0 ** 30 / (copy["FETCH_SIZE"] * 1024.0)
+        f_write = 2.0 ** 30 / (copy["WRITE_SIZE"] * 1024.0)
+        out.append(f"Calibration: a 1 GiB device copy reads {copy['FETCH_SIZE'] / 2 ** 20:.4f} "
+                   f"GiB by FETCH_SIZE and writes {copy['WRITE_SIZE'] / 2 ** 20:.4f} GiB by "
+                   f"WRITE_SIZE: FETCH_SIZE x {f_fetch:.3f}, WRITE_SIZE x {f_write:.3f}.")
+        out.append("")
+        out.append("| kernel | fetched (GB) | written (GB) | total (GB) | calls |")
+        out.append("|---|---|---|---|---|")
+        traffic = {}
+        for k in sorted(pmc):
+            fb = pmc[k]["FETCH_SIZE"] * 1024.0 * f_fetch
+            wb = pmc[k]["WRITE_SIZE"] * 1024.0 * f_write
+            out.append(f"| {k} | {fb / 1e9:.3f} | {wb / 1e9:.4f} | {(fb + wb) / 1e9:.3f} | "
+                       f"{calls} |")
+            traffic[k] = dict(bytes_per_launch=fb + wb, fetched=fb, written=wb,
+                              source_hash=source_hash(k))
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+            json.dump(traffic, f, indent=1)
+    print("\n".join(out))
+
+
 def main():
     args = parse()
+    if args.summarize:
+        return summarize(args.summarize, calls=args.steps)
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the split over several GPUs is a design, not implemented)",
@@ -515,7 +608,19 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
                                 samples_per_s=n / (ms * 1e-3),
                                 hbm_bytes_algorithmic=nbytes,
                                 gbps=nbytes / (ms * 1e-3) / 1e9,
-                                hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM)
+                                hbm_frac=nbytes / (ms * 1e-3) / PEAK_HBM,
+                                stored_bytes=vol32.nbytes)
+    # the same view from 16-voxel bricks (smaller apron) and from 16-bit storage: the
+    # algorithmic bytes are the voxels' (4 or 2 B each); stored_bytes is what the layout holds
+    for st, br in (("f32", 16), ("f16", 8), ("bf16", 8)):
+        v = svr.svr_volume_create(cube, storage=st, brick=br)
+        ms = _time(torch, lambda: svr.svr_render(v, c, lut, p), 10)
+        nb = (4 if st == "f32" else 2) * cube.numel()
+        forms[f"sparse_mip0_{st}_brick{br}"] = dict(
+            ms=ms, samples_per_s=n / (ms * 1e-3), hbm_bytes_algorithmic=nb,
+            gbps=nb / (ms * 1e-3) / 1e9, hbm_frac=nb / (ms * 1e-3) / PEAK_HBM,
+            stored_bytes=v.nbytes, stored_gbps=v.nbytes / (ms * 1e-3) / 1e9)
+        v.close()
     # the paper's in-ray 9-tap Gaussian (13 trilinear fetches per sample), view 0
     star9 = (0.2270270270, [(1.3846153846, 0.3162162162), (3.2307692308, 0.0702702703)])
     r = {}

@@ -157,6 +157,11 @@ class Volume:
     def _as_parameter_(self):
         return C.c_void_p(self.handle)
 
+    @property
+    def nbytes(self):
+        """Device bytes the volume holds (bricked storage with apron and padding)."""
+        return svr_volume_info(self)["bytes"]
+
 
 def svr_volume_create(cube, storage="f32", brick=8, nan_fill=float("nan"), stream=None):
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
