@@ -632,6 +632,24 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
         r[m] = dict(ms=ms, samples_per_s=n / (ms * 1e-3), fetches_per_s=13 * n / (ms * 1e-3),
                     fps=1e3 / ms)
     forms["star9_in_ray_gaussian"] = r
+    # the 64^3 blob cube (noise + 3 blobs), parallel view along +z at 256 x 256, dt = 0.5 (128
+    # samples per ray), ramp table: float32, float16 and bfloat16 storage
+    log("form: 64^3 blob cube")
+    c0 = torch.from_numpy(synth.blob_cube_64(0)).cuda()
+    l0, h0 = svr.svr_minmax(c0)
+    cam0 = synth.ortho_axis(64, 64, 64, 256, 256, "+z").as_f32()
+    ramp = torch.from_numpy(synth.lut_ramp(256)).cuda()
+    r0 = {}
+    for st in ("f32", "f16", "bf16"):
+        v = svr.svr_volume_create(c0, storage=st)
+        for m in ("mip0", "avip0"):
+            p0 = dict(mode=m, k=0.22, clim_lo=l0, clim_hi=h0)
+            _, ns = svr.svr_render(v, cam0, ramp, p0, samples=True)
+            n0 = int(ns.sum().item())
+            ms = _time(torch, lambda: svr.svr_render(v, cam0, ramp, p0), 50)
+            r0[f"{st}_{m}"] = dict(ms=ms, samples_per_s=n0 / (ms * 1e-3), fps=1e3 / ms)
+        v.close()
+    forms["blob64_256x256"] = r0
     # moment maps M0 / M1 / argmax over the whole spectral axis: one streaming read of the cube
     log("form: moment maps")
     mom = svr.svr_moments(cube)
