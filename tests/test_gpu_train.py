@@ -246,7 +246,7 @@ def test_descent_recovers_hidden_transfer_function(svr):
         opt.zero_grad()
         loss = sum(((svr.RenderFn.apply(cube_t, tf, c, p) - t) ** 2).sum()
                    for c, t in zip(cams, targets))
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
         if it == 60:
             break
         loss.backward()
