@@ -191,6 +191,17 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
                       const svr_lut* lut, const svr_params* params, float* rgba_out,
                       int32_t* samples_out, void* stream);
 
+/* Host-only: the number of segments svr_render splits each ray of this view into.  1 is one
+ * pass per ray.  For the MIP transfer functions without smoothing or line ratio, oblique views
+ * with few rays and many samples split each ray's samples over up to 8 workgroups, so more
+ * loads are in flight (parallel views along a volume axis stay one pass: they stream the
+ * bricks in order); a per-pixel 64-bit maximum of (s, k) keys then selects the same sample
+ * as the one-pass render (Eq. MIP, later sample on ties), and the image is bit-identical to
+ * it.  The split render runs three kernels on the stream (clear, march, finalise) and uses
+ * the output image as its scratch. */
+svr_status svr_render_segments(const svr_volume* vol, const svr_camera* cam,
+                               const svr_params* params, int32_t* segments);
+
 /* ---------------------------------------------------------------- smoothing pre-pass
  * Separable 3D smoothing (Section 4.2: the 1D kernel applied successively along x, y, z)
  * with clamp-to-edge borders and float32 accumulation.  taps_host[ntaps] (odd ntaps <=

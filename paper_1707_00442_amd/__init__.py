@@ -246,6 +246,16 @@ def svr_render(vol, camera, lut, params=None, vol2=None, out=None, samples=False
     return (out, ns) if samples else out
 
 
+def svr_render_segments(vol, camera, params=None, **kw):
+    """Segments svr_render splits each ray of this view into (1: one pass per ray)."""
+    cam = camera_struct(camera)
+    p = params_struct(params, **kw)
+    n = C.c_int32(0)
+    _check(lib().svr_render_segments(vol, C.byref(cam), C.byref(p), C.byref(n)),
+           "svr_render_segments")
+    return int(n.value)
+
+
 # ------------------------------------------------------------------------------- smoothing
 def svr_smooth_workspace(cube, ntaps):
     """Device bytes of workspace svr_smooth needs for `ntaps` taps (0 for the fused kernels)."""

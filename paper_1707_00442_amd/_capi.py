@@ -22,7 +22,7 @@ EXPORTS = (
     "svr_status_string", "svr_last_error", "svr_version", "svr_minmax", "svr_minmax_noalloc",
     "svr_volume_create", "svr_volume_destroy", "svr_volume_upload", "svr_volume_info",
     "svr_volume_clim",
-    "svr_volume_export", "svr_params_validate", "svr_render", "svr_smooth_workspace",
+    "svr_volume_export", "svr_params_validate", "svr_render", "svr_render_segments", "svr_smooth_workspace",
     "svr_smooth",
     "svr_line_ratio", "svr_moments", "svr_render_train_workspace", "svr_render_train",
     "svr_render_backward", "svr_batch_create", "svr_batch_launch", "svr_batch_info",
@@ -91,6 +91,7 @@ def load():
         "svr_volume_export": (C.c_int, [vp, vp, vp]),
         "svr_params_validate": (C.c_int, [P(Params)]),
         "svr_render": (C.c_int, [vp, vp, P(Camera), P(Lut), P(Params), vp, vp, vp]),
+        "svr_render_segments": (C.c_int, [vp, P(Camera), P(Params), P(C.c_int32)]),
         "svr_smooth_workspace": (C.c_int, [P(CubeView), i32, P(C.c_size_t)]),
         "svr_smooth": (C.c_int, [P(CubeView), P(f32), i32, vp, vp, C.c_size_t, vp]),
         "svr_line_ratio": (C.c_int, [P(CubeView), i32, i32, i32, f32, f32, f32, vp, vp]),

@@ -37,6 +37,7 @@ svr_status launch_upload(const svr_cube_view& c, const VolDesc& d, float* aux, f
 svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_camera& cam,
                          const svr_lut& lut, const svr_params& p, float* out,
                          int32_t* samples, hipStream_t stream);
+int render_segments(const svr_camera& cam, const VolDesc& v, const svr_params& p);
 svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int ntaps, void* out,
                          void* ws, hipStream_t stream);
 bool smooth_fused_taps(int ntaps);
@@ -298,6 +299,16 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
     }
     return launch_render(vol, params->ratio ? vol2 : nullptr, *cam, *lut, *params, rgba_out,
                          samples_out, S(stream));
+}
+
+svr_status svr_render_segments(const svr_volume* vol, const svr_camera* cam,
+                               const svr_params* params, int32_t* segments) {
+    SVR_CHECK(vol != nullptr && segments != nullptr, "svr_render_segments: null argument");
+    svr_status st;
+    if ((st = check_camera(cam))) return st;
+    if ((st = check_params(params, vol))) return st;
+    *segments = render_segments(*cam, vol->d, *params);
+    return SVR_OK;
 }
 
 svr_status svr_smooth_workspace(const svr_cube_view* in, int32_t ntaps, size_t* bytes) {

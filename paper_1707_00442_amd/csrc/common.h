@@ -120,9 +120,23 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
 // Workgroup b -> tile index so that each XCD (workgroups are dealt round-robin over the
 // 8 XCDs) owns one contiguous run of tiles and its L2 sees neighbouring rays.
-__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
     const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, s = b >> 3;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+// Workgroup b -> tile index for work that varies from tile to tile (rays of different
+// lengths).  Contiguous runs of kXcdRun tiles are dealt to the XCDs in turn, so each XCD owns
+// every eighth run: spread over the whole image, which balances the XCDs' work (one band per
+// XCD, as xcd_tile gives, leaves the XCDs whose bands miss the volume idle), while its L2
+// still sees runs of neighbouring rays.  The last, incomplete round of 8 runs is split as
+// xcd_tile splits a grid.
+constexpr int kXcdRun = 4;
+__host__ __device__ __forceinline__ int xcd_run_tile(int b, int nblocks) {
+    const int full = nblocks / (8 * kXcdRun) * (8 * kXcdRun);
+    if (b >= full) return full + xcd_tile(b - full, nblocks - full);
+    const int x = b & 7, s = b >> 3;
+    return ((s / kXcdRun) * 8 + x) * kXcdRun + s % kXcdRun;
 }
 
 // Ray of one pixel and its entry into the box [-0.5, n-0.5]^3, in double precision with

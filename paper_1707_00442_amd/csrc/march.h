@@ -163,6 +163,42 @@ __device__ __forceinline__ void march(const RenderArgs& a, const float4* s_lut, 
     }
 }
 
+// setFragment of the MIP transfer functions (Alg. MIP0, MIP1, MIP_RGB) from the ray's maximum
+// smax and the index kmax of its last maximal sample: MIP0 maps the maximum through the table,
+// MIP1 colours by the location's velocity coordinate, MIP_RGB by its (z, y, x); alpha per
+// mip_alpha (the Discussion's workaround for 2).
+template <int MODE>
+__device__ __forceinline__ float4 mip_fragment(const RenderArgs& a, const float4* s_lut,
+                                               const RaySeg& r, const Filt& F, float smax,
+                                               int kmax) {
+    const float n_lut = (float)(a.lut_n - 1);
+    float4 res;
+    float alpha;
+    if (MODE == SVR_MIP0) {
+        res = table(s_lut, n_lut, smax);
+        alpha = res.w;
+    } else {
+        const float km = (float)kmax;
+        const float lx = sat((fmaf(km, r.step[0], r.p0[0]) + 0.5f) / (float)a.v.nx);
+        const float ly = sat((fmaf(km, r.step[1], r.p0[1]) + 0.5f) / (float)a.v.ny);
+        const float lz = sat((fmaf(km, r.step[2], r.p0[2]) + 0.5f) / (float)a.v.nz);
+        if (MODE == SVR_MIP1) {
+            res = table(s_lut, n_lut, lz);
+        } else {
+            res = make_float4(lz, ly, lx, 0.0f);
+        }
+        alpha = smax;
+    }
+    if (a.p.mip_alpha == 1) {
+        alpha = 1.0f;
+    } else if (a.p.mip_alpha == 2) {
+        const float sthr = F.inv > 0.0f ? sat((a.p.min_t - F.lo) * F.inv) : 0.0f;
+        if (smax > sthr) alpha = 1.0f;
+    }
+    res.w = alpha;
+    return res;
+}
+
 // Transfer functions of Sections 3.1-3.3 over the sample stream of one ray (any feed).
 template <int MODE, class Feed>
 __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lut,
@@ -188,29 +224,7 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
             return active;
         });
         if (N == 0) return;
-        float alpha;
-        if (MODE == SVR_MIP0) {
-            res = table(s_lut, n_lut, smax);
-            alpha = res.w;
-        } else {
-            const float km = (float)kmax;
-            const float lx = sat((fmaf(km, r.step[0], r.p0[0]) + 0.5f) / (float)a.v.nx);
-            const float ly = sat((fmaf(km, r.step[1], r.p0[1]) + 0.5f) / (float)a.v.ny);
-            const float lz = sat((fmaf(km, r.step[2], r.p0[2]) + 0.5f) / (float)a.v.nz);
-            if (MODE == SVR_MIP1) {
-                res = table(s_lut, n_lut, lz);
-            } else {
-                res = make_float4(lz, ly, lx, 0.0f);
-            }
-            alpha = smax;
-        }
-        if (a.p.mip_alpha == 1) {
-            alpha = 1.0f;
-        } else if (a.p.mip_alpha == 2) {
-            const float sthr = F.inv > 0.0f ? sat((a.p.min_t - F.lo) * F.inv) : 0.0f;
-            if (smax > sthr) alpha = 1.0f;
-        }
-        res.w = alpha;
+        res = mip_fragment<MODE>(a, s_lut, r, F, smax, kmax);
         return;
     }
 

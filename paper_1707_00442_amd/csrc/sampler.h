@@ -193,27 +193,26 @@ struct Sampler {
 };
 
 // Samples along one ray, fetched in order: fetch number j (j = 0, 1, 2, ...) is the sample
-// at q0 + (j + base) dq.  The position is advanced in double by one step per fetch; the
-// accumulated rounding stays below 1e-9 voxel for any realistic ray length.  At steps below
-// a voxel consecutive samples often share a cell: such a sample issues no loads and value()
-// blends it from the corners of the last sample that loaded (values are taken in fetch
-// order, so those are the previous sample's corners).
+// at q0 + (j + base) dq, each position formed directly in double (one fma per axis from the
+// sample index), so a sample's position does not depend on where the stream started: a ray
+// rendered in segments (split MIP rays) samples exactly the points of the whole ray.  At
+// steps below a voxel consecutive samples often share a cell: such a sample issues no loads
+// and value() blends it from the corners of the last sample that loaded (values are taken in
+// fetch order, so those are the previous sample's corners).
 template <class S>
 struct RaySource {
     using Fetch = typename S::Fetch;
     const S& smp;
-    double px, py, pz, dqx, dqy, dqz;
+    double qx, qy, qz, dqx, dqy, dqz, kd;
     uint32_t last = 0xffffffffu;
     Fetch lc{};  // corners of the last blended sample that loaded
     __device__ __forceinline__ RaySource(const S& s, const RaySeg& r, float base)
-        : smp(s), px(fma((double)base, r.dq[0], r.q0[0])),
-          py(fma((double)base, r.dq[1], r.q0[1])), pz(fma((double)base, r.dq[2], r.q0[2])),
-          dqx(r.dq[0]), dqy(r.dq[1]), dqz(r.dq[2]) {}
+        : smp(s), qx(r.q0[0]), qy(r.q0[1]), qz(r.q0[2]), dqx(r.dq[0]), dqy(r.dq[1]),
+          dqz(r.dq[2]), kd((double)base) {}
     __device__ __forceinline__ Fetch next() {
-        const Fetch f = smp.fetch_after(px, py, pz, last);
-        px += dqx;
-        py += dqy;
-        pz += dqz;
+        const Fetch f = smp.fetch_after(fma(kd, dqx, qx), fma(kd, dqy, qy), fma(kd, dqz, qz),
+                                        last);
+        kd += 1.0;
         return f;
     }
     __device__ __forceinline__ float value(const Fetch& f) {

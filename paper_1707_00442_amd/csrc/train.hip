@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void train_fwd_kernel(const TrainArgs a) {
     __shared__ float4 s_tf[kTrainMaxTf + 1];
     stage_table(s_tf, a.tf, a.tf_n);
     __syncthreads();
-    const int t = xcd_tile((int)blockIdx.x, a.nblocks);
+    const int t = xcd_run_tile((int)blockIdx.x, a.nblocks);
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int px = tx * kTile + (w & 1) * 8 + (l & 7);
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void train_bwd_kernel(const TrainArgs a) {
         for (int i = threadIdx.x; i < kBox; i += kBlock) s_box[i] = 0.0f;
     __syncthreads();
 
-    const int t = xcd_tile((int)blockIdx.x, a.nblocks);
+    const int t = xcd_run_tile((int)blockIdx.x, a.nblocks);
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int px = tx * kTile + (w & 1) * 8 + (l & 7);

@@ -73,6 +73,9 @@ def test_full_frame_transfer_functions(svr, full, mode, view):
     params = dict(mode=mode, k=0.22, filter="clip", min_t=3.0)
     lo, hi = full["lo"], full["hi"]
     print(f"[full] {mode} view {view}", flush=True)
+    # the MIP renders of these views split each ray in two segments, the AVIP ones do not
+    assert svr.svr_render_segments(full["vol"], cam, params) == (2 if mode.startswith("mip")
+                                                                  else 1)
     got, ns, pix = _render_sampled(svr, full["vol"], cam, lut, params, lo, hi, seed=view)
     err, frag, nert = compare_render(oracle, got, ns, full["cube"], cam, lut, params, lo, hi,
                                      pixels=pix, margins=margins(lo, hi, params),
@@ -132,11 +135,13 @@ def test_full_frame_half_storage(svr, full, storage, mode):
 
 def test_full_sparse_parallel_view(svr, full):
     """The low-density view (parallel along +z, 256 x 256 over the 512 x 512 face, dt = 1):
-    every pixel against the oracle."""
+    every pixel against the oracle.  A parallel view along a volume axis renders each ray in
+    one pass."""
     cam = synth.ortho_axis(NX, NY, NZ, 256, 256, "+z").as_f32()
     lut = synth.lut_heat(256)
     params = dict(mode="mip0", k=0.22, filter="clip", min_t=3.0, dt=1.0)
     lo, hi = full["lo"], full["hi"]
+    assert svr.svr_render_segments(full["vol"], cam, params) == 1
     img, ns = svr.svr_render(full["vol"], cam, to_cuda(lut), params, clim_lo=lo, clim_hi=hi,
                              samples=True)
     svr.svr_sync()
@@ -146,6 +151,35 @@ def test_full_sparse_parallel_view(svr, full):
     err, frag, _ = compare_render(oracle, got, ns, full["cube"], cam, lut, params, lo, hi,
                                   margins=margins(lo, hi, params))
     print(f"[full sparse] max err {err:.3e} fragile {frag.sum()}", flush=True)
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("mode", ["mip0", "mip1", "miprgb"])
+def test_full_small_oblique_view_split(svr, full, mode):
+    """A 256 x 256 rotation view of the full cube at dt = 0.5: each ray split into 8 segments
+    (about 2,400 samples per ray); sampled pixels against the oracle and the whole image
+    bit-identical to the batched one-pass render."""
+    import torch
+    cam = synth.rotation_views(NX, NY, NZ, 256, 256)[3].as_f32()
+    lut = synth.lut_heat(256)
+    params = dict(mode=mode, filter="clip", min_t=3.0, mip_alpha=2)
+    lo, hi = full["lo"], full["hi"]
+    assert svr.svr_render_segments(full["vol"], cam, params) == 8
+    img, ns = svr.svr_render(full["vol"], cam, to_cuda(lut), params, clim_lo=lo, clim_hi=hi,
+                             samples=True)
+    b = svr.svr_batch_create([full["vol"]], [cam], to_cuda(lut),
+                             dict(params, clim_lo=lo, clim_hi=hi), tune=0)
+    b.launch()
+    svr.svr_sync()
+    assert torch.equal(b.outs[0], img)
+    b.close()
+    got = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    ns = ns.cpu().numpy().ravel()
+    pix = _sample_pixels(ns, 1000, seed=11)
+    err, frag, _ = compare_render(oracle, got[pix], ns[pix], full["cube"], cam, lut, params, lo,
+                                  hi, pixels=pix, margins=margins(lo, hi, params),
+                                  cond_tol=COND_TOL)
+    print(f"[full split] {mode} max err {err:.3e} fragile {frag.sum()}", flush=True)
     assert err <= TOL32
 
 
@@ -309,6 +343,8 @@ def test_render_volume_beyond_4gib(svr):
     lut = to_cuda(lut_np)
     for mode in MODES:
         p = dict(mode=mode, k=0.1)
+        # the MIP renders of this 960 x 540 view split each ray in two (64-bit addressing)
+        assert (svr.svr_render_segments(vol, cam, p) > 1) == mode.startswith("mip")
         img, ns = svr.svr_render(vol, cam, lut, p, clim_lo=lo, clim_hi=hi, samples=True)
         svr.svr_sync()
         got = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
