@@ -98,7 +98,8 @@ def parse():
     ap.add_argument("--summarize", default=None, metavar="DIR",
                     help="summarise rocprofv3 output written under DIR (trace/ from a "
                          "--kernel-trace --stats run of the step, pmc_<kernel>_<COUNTER>/ from "
-                         "--pmc runs of --profile <kernel>) into markdown on stdout and "
+                         "--pmc runs of --profile <kernel>, and sq_/ta_/tcp_<kernel>/ from the "
+                         "three render counter passes) into markdown on stdout and "
                          "profiles/traffic.json; no GPU needed")
     ap.add_argument("--profile", default=None,
                     help="run only this kernel on the main workload, --steps times (for "
@@ -156,7 +157,8 @@ def load_traffic(kernel):
 
 # kernels each --profile mode launches per call (rocprofv3 kernel-name prefixes)
 PROFILE_KERNELS = {
-    "render": ("svr::render_kernel<",),
+    "render": ("svr::render_kernel<", "svr::split_clear_kernel", "svr::render_split_kernel<",
+               "svr::split_finalize_kernel<"),
     "smooth": ("svr::smooth_fused_kernel<",),
     "upload": ("svr::upload_init", "svr::brick_group_kernel<", "svr::upload_final<",
                "svr::upload_fill<"),
@@ -180,16 +182,24 @@ def _kernel_name(name):
 
 def _per_call(path, kernel, calls):
     """Counter value per call of `kernel` (KiB): the last `calls` dispatches of each of the
-    kernels that call launches, summed over those kernels, averaged over the calls."""
+    kernels that call launches, summed over those kernels, averaged over the calls.  Kernels
+    of the family that the call does not launch (the split MIP kernels of a one-pass render)
+    have no dispatches and are skipped."""
     import csv
     rows = list(csv.DictReader(open(path)))
     total = 0.0
+    found = 0
     for prefix in PROFILE_KERNELS[kernel_family(kernel)]:
         vals = [float(r["Counter_Value"]) for r in rows
                 if _kernel_name(r["Kernel_Name"]).startswith(prefix)]
+        if not vals:
+            continue
         if len(vals) < calls:
             raise SystemExit(f"{path}: {len(vals)} dispatches of {prefix}, expected {calls}")
         total += sum(vals[-calls:])
+        found += 1
+    if not found:
+        raise SystemExit(f"{path}: no dispatches of the {kernel} kernels")
     return total / calls
 
 
@@ -237,7 +247,61 @@ def summarize(d, calls=20):
                               source_hash=source_hash(k))
         with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
             json.dump(traffic, f, indent=1)
+    out += _counter_tables(d, calls)
     print("\n".join(out))
+
+
+def _counter_tables(d, calls):
+    """Render counter passes (sq_<kernel>/, ta_<kernel>/, tcp_<kernel>/ under d): means per
+    call summed over the kernels one call launches, and the derived shares (VALU issue =
+    SQ_INSTS_VALU x 4 / (1024 SIMDs x C), C = GRBM_GUI_ACTIVE / 8 cycles per launch)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    kernels = sorted({os.path.basename(p).split("_", 1)[1]
+                      for p in glob.glob(os.path.join(d, "sq_*")) if os.path.isdir(p)})
+    if not kernels:
+        return []
+    res = {}
+    for k in kernels:
+        vals, ms = defaultdict(float), 0.0
+        for grp in ("sq", "ta", "tcp"):
+            path = glob.glob(os.path.join(d, f"{grp}_{k}", "*counter_collection.csv"))[0]
+            rows = list(csv.DictReader(open(path)))
+            for prefix in PROFILE_KERNELS[kernel_family(k)]:
+                by = defaultdict(dict)
+                for r in rows:
+                    if _kernel_name(r["Kernel_Name"]).startswith(prefix):
+                        by[int(r["Dispatch_Id"])][r["Counter_Name"]] = (
+                            float(r["Counter_Value"]),
+                            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                ids = sorted(by)[-calls:]
+                for i in ids:
+                    for c, (v, _) in by[i].items():
+                        vals[c] += v / calls
+                if grp == "ta" and ids:
+                    ms += sum(next(iter(by[i].values()))[1] for i in ids) / calls / 1e6
+        res[k] = (vals, ms)
+    out = ["", "| kernel | ms | clock (GHz) | waves | VALU instr / wave | loads / wave | "
+           "VALU issue | TA busy | waiting | L1 lookups / load | to L2 | L1 pending stall | "
+           "TD stall on L2 |", "|" + "---|" * 13]
+    for k, (v, ms) in res.items():
+        c = v["GRBM_GUI_ACTIVE"] / 8
+        w = v["SQ_WAVES"]
+        out.append(
+            f"| {k} | {ms:.3f} | {c / (ms * 1e-3) / 1e9:.2f} | {w:.0f} | "
+            f"{v['SQ_INSTS_VALU'] / w:.0f} | {v['SQ_INSTS_VMEM_RD'] / w:.0f} | "
+            f"{v['SQ_INSTS_VALU'] * 4 / (1024 * c):.0%} | {v['TA_BUSY_avr'] / c:.0%} | "
+            f"{v['SQ_WAIT_INST_ANY'] / v['SQ_WAVE_CYCLES']:.0%} | "
+            f"{v['TCP_TOTAL_CACHE_ACCESSES_sum'] / v['SQ_INSTS_VMEM_RD']:.1f} | "
+            f"{v['TCP_TCC_READ_REQ_sum'] / v['TCP_TOTAL_CACHE_ACCESSES_sum']:.1%} | "
+            f"{v['TCP_PENDING_STALL_CYCLES_sum'] / (256 * c):.0%} | "
+            f"{v['TD_TC_STALL_sum'] / (256 * c):.0%} |")
+    keys = sorted(set().union(*[set(v) for v, _ in res.values()]))
+    out += ["", "| kernel | " + " | ".join(keys) + " |", "|---|" + "---|" * len(keys)]
+    for k, (v, _) in res.items():
+        out.append(f"| {k} | " + " | ".join(f"{v[c]:.4g}" for c in keys) + " |")
+    return out
 
 
 def main():
