@@ -96,7 +96,14 @@ template <> struct Elem<SVR_F32> {
 template <> struct Elem<SVR_F16> {
     using T = _Float16;
     static __device__ __forceinline__ float get(const T* p, uint32_t i) { return (float)p[i]; }
-    static __device__ __forceinline__ T put(float v) { return (_Float16)v; }  // RNE
+    // The float32 value rounded to nearest even.  The empty asm hides where v came from, so
+    // the compiler cannot fold the FMA that produced it into a mixed-precision FMA that rounds
+    // the exact result to half once: which of the two roundings a store got would then depend
+    // on the code around it (one half ulp apart at ties).
+    static __device__ __forceinline__ T put(float v) {
+        asm("" : "+v"(v));
+        return (_Float16)v;
+    }
 };
 template <> struct Elem<SVR_BF16> {
     using T = uint16_t;

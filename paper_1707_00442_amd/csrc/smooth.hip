@@ -150,7 +150,7 @@ constexpr int kXyR = 8;  // x-phase outputs per lane
 // with no intermediate cube.  The sums are the ordered sums of the two-kernel form (x, then
 // y, then z, each sum_j g[j] v[j] by fma from j = 0 up), so the result is bit-identical.
 constexpr int kFzTx = 64;  // tile width (x)
-constexpr int kFzTy = 16;  // tile height (y)
+constexpr int kFzTy = 16;  // rows of y outputs the lanes compute (4 waves x kFzRy)
 constexpr int kFzRy = 4;   // outputs per lane along y (ring depth kFzRy x T registers)
 constexpr int kFzZ = 128;  // output planes per workgroup
 // Long filters keep the ring as a shift register (T x kFzRy moves per plane); short ones
@@ -158,18 +158,27 @@ constexpr int kFzZ = 128;  // output planes per workgroup
 // code grows as T^2 and stops fitting the instruction cache).
 template <int T>
 constexpr bool kFzShift = T > 13;
+constexpr int kFzU = 4;  // planes per shift of the shift-register ring
+// Rows of the tile written: the x phase filters kFzTy + T - 1 rows in units of 8 outputs, 8
+// units per row; up to 32 rows that is one unit per lane.  At 19 taps 16 rows would need 34
+// (a second pass for one wave while the others wait at the barrier), so the tile keeps 14
+// rows (32 filtered) and the lanes of the last two rows compute outputs that are not stored.
+template <int T>
+constexpr int kFzRows = kFzTy + T - 1 > 32 ? 33 - T : kFzTy;
 
 template <int DT_IN, int DT_OUT, int T>
 __global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
     const typename Elem<DT_IN>::T* in, typename Elem<DT_OUT>::T* out, int32_t nx, int32_t ny,
     int32_t nz, int32_t tiles_x, int32_t ntiles, int32_t nblocks, const FixedTaps<T> g) {
     constexpr int r = T / 2;
-    constexpr int AW = kFzTx + T - 1, AH = kFzTy + T - 1;
+    constexpr int TY = kFzRows<T>;
+    constexpr int AW = kFzTx + T - 1, AH = TY + T - 1;
     __shared__ float A[AH * AW];
-    __shared__ float B[AH * kFzTx];
+    // the y phase of the rows past TY reads up to row kFzTy + T - 2 (values not stored)
+    __shared__ float B[(kFzTy + T - 1) * kFzTx];
     const int b = xcd_tile((int)blockIdx.x, nblocks);  // neighbouring tiles on one XCD
     const int tile = b % ntiles, zc = b / ntiles;
-    const int x0 = (tile % tiles_x) * kFzTx, y0 = (tile / tiles_x) * kFzTy;
+    const int x0 = (tile % tiles_x) * kFzTx, y0 = (tile / tiles_x) * TY;
     const int z0 = zc * kFzZ;
     const int64_t plane = (int64_t)nx * ny;
     const int xl = threadIdx.x & (kFzTx - 1);     // this lane's column
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
 #pragma unroll
                 for (int q = 0; q < kFzRy; ++q) {
                     const int gy = y0 + yg + q;
-                    if (gy < ny)
+                    if (yg + q < TY && gy < ny)
                         out[(int64_t)zo * plane + (int64_t)gy * nx + gxo] = Elem<DT_OUT>::put(acc[q]);
                 }
             }
@@ -258,13 +267,21 @@ __global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
         __syncthreads();  // A holds the next plane; B no longer read
     };
     if constexpr (kFzShift<T>) {
-        // shift register: ring[0] is the oldest plane; code size independent of T
-        for (int s = 0; s < nsl; ++s) {
+        // shift register advanced kFzU planes at a time: before a group of kFzU planes,
+        // slots 0 .. T-2 take the last T-1 planes (oldest first); plane u of the group goes to
+        // slot T-1+u and its z sum reads slots u .. u+T-1.  (T-1) x kFzRy moves per group
+        // instead of per plane; the code holds kFzU copies of the plane step.
+        constexpr int U = kFzU;
+        float sr[T + U - 1][kFzRy];
+        for (int s0 = 0; s0 < nsl; s0 += U) {
 #pragma unroll
             for (int j = 0; j + 1 < T; ++j)
 #pragma unroll
-                for (int q = 0; q < kFzRy; ++q) ring[j][q] = ring[j + 1][q];
-            step(s, ring[T - 1], [&](int j) -> const float* { return ring[j]; });
+                for (int q = 0; q < kFzRy; ++q) sr[j][q] = sr[j + U][q];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (s0 + u < nsl)  // uniform over the workgroup
+                    step(s0 + u, sr[T - 1 + u], [&](int j) -> const float* { return sr[u + j]; });
         }
     } else {
         // rotating ring unrolled T times: plane s sits in slot s mod T
@@ -280,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
 template <int T, int DT_IN, int DT_OUT>
 static svr_status smooth_fused_launch(const svr_cube_view& c, const FixedTaps<T>& g, void* out,
                                       hipStream_t stream) {
-    const int tiles_x = (c.nx + kFzTx - 1) / kFzTx, tiles_y = (c.ny + kFzTy - 1) / kFzTy;
+    const int tiles_x = (c.nx + kFzTx - 1) / kFzTx;
+    const int tiles_y = (c.ny + kFzRows<T> - 1) / kFzRows<T>;
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     const int64_t nb = ntiles * ((c.nz + kFzZ - 1) / kFzZ);
     if (nb > 0x7fffffff) return SVR_EUNSUPPORTED;

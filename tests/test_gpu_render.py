@@ -568,6 +568,49 @@ def test_smooth_parity(svr, taps_name, dtype):
     del torch
 
 
+def test_smooth_19_taps_several_tiles(svr):
+    """The 19-tap fused kernel (14-row tiles) over a cube spanning several x tiles, four y
+    tiles (the last ragged) and two runs of output planes, against the oracle."""
+    from oracle import taps as T
+    g32 = T.gauss(3.0).astype(np.float32)
+    assert len(g32) == 19
+    cube = synth.blob_cube(140, 4, seed=8)[:, :45, :130].copy()
+    out = svr.svr_smooth(to_cuda(cube), g32)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.smooth(cube, g32.astype(np.float64))
+    bound = 3 * len(g32) * 2.0 ** -24 * np.abs(g32).sum() ** 3 * np.abs(cube).max()
+    err = np.abs(got - ref)
+    print(f"[smooth 19 taps {cube.shape}] max err {err.max():.3e} (bound {bound:.3e})",
+          flush=True)
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("taps_name", ["binomial5", "gauss1", "gauss3"])
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_smooth_fused_equals_generic(svr, taps_name, dtype):
+    """The fused single-pass kernel (5, 7, 19 taps) gives the values of the same taps padded
+    with two zeros on each side (9 taps: the fused kernel again; 11 and 23: the generic
+    three-pass form): the padding adds products that are exactly zero, and every form sums x,
+    then y, then z, each from tap 0 up."""
+    from oracle import taps as T
+    import torch
+    g = {"binomial5": T.binomial(5), "gauss1": T.gauss(1.0), "gauss3": T.gauss(3.0)}[taps_name]
+    g32 = g.astype(np.float32)
+    padded = np.concatenate([np.zeros(2, np.float32), g32, np.zeros(2, np.float32)])
+    probe = torch.empty(1, 1, 1, device="cuda")
+    assert svr.svr_smooth_workspace(probe, len(g32)) == 0
+    assert (svr.svr_smooth_workspace(probe, len(padded)) > 0) == (len(padded) != 9)
+    cube = synth.blob_cube(45, 3, seed=9)[:, :31, :70].copy()
+    t = to_cuda(quant.dequantize(cube, dtype))
+    if dtype == "f16":
+        t = t.half()
+    a = svr.svr_smooth(t, g32).float()
+    b = svr.svr_smooth(t, padded).float()
+    # equal up to the sign of zero (-0 + +0 = +0)
+    assert torch.equal(a, b), f"max diff {(a - b).abs().max().item():.3e}"
+    del torch
+
+
 def test_smooth_delta_and_constant(svr):
     from oracle import taps as T
     g = T.gauss(2.0).astype(np.float32)
