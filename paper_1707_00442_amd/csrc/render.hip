@@ -166,11 +166,13 @@ static SplitFn pick_split_any(int dtype, int brick, bool wide, float dt, int mod
 // 512 x 512 x 1024 cube at dt = 0.5, a 256 x 256 view ran 1.33x faster in 8 segments and the
 // 1920 x 1080 views 6% faster in 2; a 512 x 512 view was unchanged.  The target is about
 // 2^21 ray segments (8 ray waves per SIMD, in about two rounds at the MIP kernels' two waves
-// per SIMD), at most 8 segments, each of at least 64 samples.  Parallel views along a volume
-// axis are excluded: their quarter-waves read whole cache lines in brick order, one pass
-// already streams at the HBM limit, and split into 2-8 concurrent streams the low-density
-// view ran 1.3-1.6x slower.  Below about 2^24 samples a render is launch-bound and stays one
-// pass.
+// per SIMD), at most 8 segments, each of at least 256 samples on the longest ray: each
+// segment repeats the ray setup and fills and drains the fetch pipeline, and 1000 x 1000
+// views of a 128^3 cube (rays of up to 222 samples) ran 13% slower in 3 segments.  Parallel
+// views along a volume axis are excluded: their quarter-waves read whole cache lines in
+// brick order, one pass already streams at the HBM limit, and split into 2-8 concurrent
+// streams the low-density view ran 1.3-1.6x slower.  Below about 2^24 samples a render is
+// launch-bound and stays one pass.
 static bool axis_parallel(const svr_camera& cam) {
     if (cam.type != 0) return false;
     const double n = sqrt((double)cam.W[0] * cam.W[0] + (double)cam.W[1] * cam.W[1] +
@@ -188,7 +190,7 @@ int render_segments(const svr_camera& cam, const VolDesc& v, const svr_params& p
                            (double)p.dt;
     if (rays * longest < 16777216.0) return 1;
     const double want = ceil(2097152.0 / rays);
-    const double most = floor(longest / 64.0);
+    const double most = floor(longest / 256.0);
     return (int)fmax(1.0, fmin(8.0, fmin(want, most)));
 }
 
