@@ -1,5 +1,7 @@
 // Separable 3D smoothing pre-pass (Section 4.2: the 1D kernel applied successively along
 // each axis) and the voxel-wise line-ratio pass (Section 4.5).  Streaming, HBM-bound.
+#include <type_traits>
+
 #include "common.h"
 
 namespace svr {
@@ -340,6 +342,15 @@ svr_status launch_smooth(const svr_cube_view& c, const float* taps_host, int nta
 }
 
 // ------------------------------------------------------------------------- line ratio
+// One voxel of the ratio pass (Section 4.5): clip each line at its threshold to DATAMIN, then
+// b / a where a > 0, else DATAMIN.
+__device__ __forceinline__ float ratio_of(float a, float b, float min_a, float min_b,
+                                          float datamin) {
+    if (a < min_a) a = datamin;
+    if (b < min_b) b = datamin;
+    return a > 0.0f ? b / a : datamin;
+}
+
 template <int DT>
 __global__ __launch_bounds__(kBlock) void line_ratio_kernel(const typename Elem<DT>::T* cube,
                                                             int32_t nx, int64_t sx, int64_t sy,
@@ -351,16 +362,96 @@ __global__ __launch_bounds__(kBlock) void line_ratio_kernel(const typename Elem<
     if (x >= nx) return;
     const int y = blockIdx.y, j = blockIdx.z;
     const int64_t off = (int64_t)y * sy + (int64_t)x * sx;
-    float a = Elem<DT>::get(cube + (int64_t)(z0a + j) * sz + off, 0);
-    float b = Elem<DT>::get(cube + (int64_t)(z0b + j) * sz + off, 0);
-    if (a < min_a) a = datamin;
-    if (b < min_b) b = datamin;
-    out[((int64_t)j * ny + y) * nx + x] = a > 0.0f ? b / a : datamin;
+    const float a = Elem<DT>::get(cube + (int64_t)(z0a + j) * sz + off, 0);
+    const float b = Elem<DT>::get(cube + (int64_t)(z0b + j) * sz + off, 0);
+    out[((int64_t)j * ny + y) * nx + x] = ratio_of(a, b, min_a, min_b, datamin);
+}
+
+// Contiguous cubes: the windows are two flat runs of nzw planes, so out[i] pairs element
+// z0a * plane + i with z0b * plane + i.  Four voxels per lane (16-byte float32 loads and
+// stores, 8-byte 16-bit loads) over a grid-stride loop, two groups in flight per lane.
+template <int DT>
+__global__ __launch_bounds__(kBlock) void line_ratio_vec4_kernel(
+    const typename Elem<DT>::T* cube, int64_t off_a, int64_t off_b, int64_t n4, float min_a,
+    float min_b, float datamin, float4* out) {
+    using T = typename Elem<DT>::T;
+    using V = typename std::conditional<DT == SVR_F32, float4, uint2>::type;
+    const V* va = reinterpret_cast<const V*>(cube + off_a);
+    const V* vb = reinterpret_cast<const V*>(cube + off_b);
+    auto unpack = [](const V& w, float (&f)[4]) {
+        if constexpr (DT == SVR_F32) {
+            f[0] = w.x; f[1] = w.y; f[2] = w.z; f[3] = w.w;
+        } else {
+            const T* h = reinterpret_cast<const T*>(&w);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f[q] = Elem<DT>::get(h, q);
+        }
+    };
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += 2 * stride) {
+        const int64_t i2 = i + stride;
+        const bool two = i2 < n4;
+        const V a0 = va[i], b0 = vb[i];
+        V a1{}, b1{};
+        if (two) {
+            a1 = va[i2];
+            b1 = vb[i2];
+        }
+        float fa[4], fb[4];
+        unpack(a0, fa);
+        unpack(b0, fb);
+        out[i] = make_float4(ratio_of(fa[0], fb[0], min_a, min_b, datamin),
+                             ratio_of(fa[1], fb[1], min_a, min_b, datamin),
+                             ratio_of(fa[2], fb[2], min_a, min_b, datamin),
+                             ratio_of(fa[3], fb[3], min_a, min_b, datamin));
+        if (two) {
+            unpack(a1, fa);
+            unpack(b1, fb);
+            out[i2] = make_float4(ratio_of(fa[0], fb[0], min_a, min_b, datamin),
+                                  ratio_of(fa[1], fb[1], min_a, min_b, datamin),
+                                  ratio_of(fa[2], fb[2], min_a, min_b, datamin),
+                                  ratio_of(fa[3], fb[3], min_a, min_b, datamin));
+        }
+    }
+}
+
+template <int DT>
+static void line_ratio_vec4(const svr_cube_view& c, int64_t off_a, int64_t off_b, int64_t n4,
+                            float min_a, float min_b, float datamin, float* out,
+                            hipStream_t stream) {
+    // enough workgroups for every CU several times over; each lane then loops
+    const int64_t want = (n4 + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(line_ratio_vec4_kernel<DT>, dim3(grid), dim3(kBlock), 0, stream,
+                       static_cast<const typename Elem<DT>::T*>(c.data), off_a, off_b, n4,
+                       min_a, min_b, datamin, reinterpret_cast<float4*>(out));
 }
 
 svr_status launch_line_ratio(const svr_cube_view& c, int z0a, int z0b, int nzw, float min_a,
                              float min_b, float datamin, float* out, hipStream_t stream) {
     const bool contig = c.sx == 0 && c.sy == 0 && c.sz == 0;
+    {
+        // the vector path: contiguous cube, planes of a multiple of 4 voxels, and the
+        // cube and output aligned to the vector size
+        const int64_t plane = (int64_t)c.nx * c.ny;
+        const size_t es = c.dtype == SVR_F32 ? 4 : 2;
+        const bool aligned = ((uintptr_t)c.data % (4 * es)) == 0 && ((uintptr_t)out % 16) == 0;
+        if (contig && plane % 4 == 0 && aligned && nzw > 0 && plane > 0) {
+            const int64_t n4 = plane * nzw / 4;
+            const int64_t oa = (int64_t)z0a * plane, ob = (int64_t)z0b * plane;
+            switch (c.dtype) {
+                case SVR_F16:
+                    line_ratio_vec4<SVR_F16>(c, oa, ob, n4, min_a, min_b, datamin, out, stream);
+                    break;
+                case SVR_BF16:
+                    line_ratio_vec4<SVR_BF16>(c, oa, ob, n4, min_a, min_b, datamin, out, stream);
+                    break;
+                default:
+                    line_ratio_vec4<SVR_F32>(c, oa, ob, n4, min_a, min_b, datamin, out, stream);
+            }
+            return hip_fail(hipGetLastError(), "line_ratio launch");
+        }
+    }
     const int64_t sx = contig ? 1 : c.sx;
     const int64_t sy = contig ? (int64_t)c.nx : c.sy;
     const int64_t sz = contig ? (int64_t)c.nx * c.ny : c.sz;

@@ -528,6 +528,40 @@ def test_line_ratio_pass(svr, dtype):
     del torch
 
 
+@pytest.mark.parametrize("layout", ["odd_plane", "misaligned", "strided"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_line_ratio_pass_other_layouts(svr, layout, dtype):
+    """The voxel-wise ratio pass on cubes the four-voxel vector path does not take (planes of
+    an odd voxel count, a contiguous cube one element off the vector alignment, a strided
+    view): same values as the oracle, and as the vector path where both apply."""
+    import torch
+    full = quant.dequantize(synth.blob_cube(44, 3, seed=4), dtype)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    if layout == "odd_plane":
+        cube = full[:, :29, :37].copy()
+        t = to_cuda(cube).to(tdt)
+    elif layout == "misaligned":
+        cube = full[:, :32, :40].copy()
+        flat = torch.empty(cube.size + 1, dtype=tdt, device="cuda")
+        flat[1:] = to_cuda(cube).reshape(-1).to(tdt)
+        t = flat[1:].view(cube.shape)
+        assert t.is_contiguous() and t.data_ptr() % 8 != 0
+    else:
+        cube = full[:, 2:34, 1:41].copy()
+        t = to_cuda(full).to(tdt)[:, 2:34, 1:41]
+        assert not t.is_contiguous()
+    for (za, zb, n, ma, mb) in [(3, 30, 12, -np.inf, -np.inf), (5, 6, 20, 0.5, 1.0)]:
+        out = svr.svr_line_ratio(t, za, zb, n, ma, mb, datamin=-4.5)
+        ref = oracle.line_ratio(cube, za, zb, n, ma, mb, datamin=-4.5)
+        got = out.cpu().numpy().astype(np.float64)
+        rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
+        assert rel.max() <= 2.0 ** -24 * 1.01
+        if layout != "odd_plane":
+            vec = svr.svr_line_ratio(t.contiguous().clone(), za, zb, n, ma, mb, datamin=-4.5)
+            assert torch.equal(vec, out)
+    del torch
+
+
 # ----------------------------------------------------------------------------- smoothing
 @pytest.mark.parametrize("taps_name", ["binomial3", "binomial5", "paper9", "binomial13", "gauss1",
                                        "gauss3", "gauss4"])
