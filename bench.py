@@ -163,7 +163,7 @@ PROFILE_KERNELS = {
     "upload": ("svr::upload_init", "svr::brick_group_kernel<", "svr::upload_final<",
                "svr::upload_fill<"),
     "moments": ("svr::moments_kernel<",),
-    "line_ratio": ("svr::line_ratio_kernel<",),
+    "line_ratio": ("svr::line_ratio_kernel<", "svr::line_ratio_vec4_kernel<"),
     "copy": ("__amd_rocclr_copyBuffer",),
 }
 
