@@ -66,27 +66,37 @@ struct BoxRing {
 // and box into one kernel and picks per launch from box_arm.
 enum { kSmoothNone = 0, kSmoothBox = 1, kSmoothStar = 2, kSmoothAuto = 3 };
 
-// Run alive = per_sample(k, value, active) over the ray's samples k = 0 .. N-1, the value
-// being the raw sample, its box mean or its in-ray Gaussian.
+// Run alive = per_sample(j, value, active) over the n samples k0 + j (j = 0 .. n-1) of a ray,
+// the value being the raw sample or its box mean (the raw stream then starts at k0 - arm and
+// fills the ring first, so a run of samples gets the means of the whole ray).
 template <int SMOOTH, int NS, class S, class Fn>
-__device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, int arm, float* ring,
-                                               const svr_params& st, Fn&& per_sample) {
+__device__ __forceinline__ void for_each_value_from(const S& smp, const RaySeg& r, int k0, int n,
+                                                    int arm, float* ring, Fn&& per_sample) {
+    static_assert(SMOOTH == kSmoothNone || SMOOTH == kSmoothBox, "raw or box values");
     if (SMOOTH == kSmoothNone) {
-        drive<NS>(RaySource<S>(smp, r, 0.0f), r.n, per_sample);
-        return;
-    }
-    if (SMOOTH == kSmoothStar) {  // values complete at fetch time: one ahead is enough
-        drive<2>(StarSource<S>(smp, st, r), r.n, per_sample);
+        drive<NS>(RaySource<S>(smp, r, (float)k0), n, per_sample);
         return;
     }
     BoxRing box(ring, arm);
     const int lead = 2 * arm;
-    drive<NS>(RaySource<S>(smp, r, (float)(-arm)), r.n > 0 ? r.n + lead : 0,
+    drive<NS>(RaySource<S>(smp, r, (float)(k0 - arm)), n > 0 ? n + lead : 0,
           [&](int j, float raw, bool active) -> bool {
               float mean;
               if (!box.push(j, raw, mean)) return active;  // still filling the window
               return per_sample(j - lead, mean, active);
           });
+}
+
+// Run alive = per_sample(k, value, active) over the ray's samples k = 0 .. N-1, the value
+// being the raw sample, its box mean or its in-ray Gaussian.
+template <int SMOOTH, int NS, class S, class Fn>
+__device__ __forceinline__ void for_each_value(const S& smp, const RaySeg& r, int arm, float* ring,
+                                               const svr_params& st, Fn&& per_sample) {
+    if constexpr (SMOOTH == kSmoothStar) {  // values complete at fetch time: one ahead is enough
+        drive<2>(StarSource<S>(smp, st, r), r.n, per_sample);
+    } else {
+        for_each_value_from<SMOOTH, NS>(smp, r, 0, r.n, arm, ring, per_sample);
+    }
 }
 
 // The sample stream of one ray through the bricked volume: feed.run(body) delivers

@@ -68,8 +68,9 @@ __global__ void split_clear_kernel(unsigned long long* key, int64_t npix) {
     if (i < npix) key[2 * i] = 0ull;
 }
 
-template <int MODE, int DT, int C, bool WIDE, bool REUSE>
+template <int MODE, int DT, int C, bool WIDE, bool REUSE, int SMOOTH>
 __global__ __launch_bounds__(kBlock) void render_split_kernel(const RenderArgs a, int32_t nseg) {
+    extern __shared__ float4 smem[];  // the box ring (SMOOTH = kSmoothBox)
     const int tiles = a.nblocks;
     const int b = (int)blockIdx.x;
     const int seg = b / tiles;
@@ -90,7 +91,8 @@ __global__ __launch_bounds__(kBlock) void render_split_kernel(const RenderArgs a
     const Smp smp(a.v);
     float smax = -INFINITY;
     int kmax = 0;
-    drive<drive_slots<MODE, DT>()>(RaySource<Smp>(smp, r, (float)k0), n,
+    float* ring = reinterpret_cast<float*>(smem) + threadIdx.x;
+    for_each_value_from<SMOOTH, drive_slots<MODE, DT>()>(smp, r, k0, n, a.p.box_arm, ring,
                                    [&](int k, float v, bool active) -> bool {
                                        const float s = F(v);
                                        if (MODE == SVR_MIP0) {
@@ -137,21 +139,28 @@ __global__ __launch_bounds__(kBlock) void split_finalize_kernel(const RenderArgs
 
 using SplitFn = void (*)(RenderArgs, int32_t);
 
+template <int DT, int C, bool WIDE, bool REUSE, int SMOOTH>
+static SplitFn pick_split_mode(int mode) {
+    if (mode == SVR_MIP0) return render_split_kernel<SVR_MIP0, DT, C, WIDE, REUSE, SMOOTH>;
+    if (mode == SVR_MIP1) return render_split_kernel<SVR_MIP1, DT, C, WIDE, REUSE, SMOOTH>;
+    return render_split_kernel<SVR_MIPRGB, DT, C, WIDE, REUSE, SMOOTH>;
+}
+
 template <int DT, int C, bool WIDE, bool REUSE>
-static SplitFn pick_split(int mode) {
-    if (mode == SVR_MIP0) return render_split_kernel<SVR_MIP0, DT, C, WIDE, REUSE>;
-    if (mode == SVR_MIP1) return render_split_kernel<SVR_MIP1, DT, C, WIDE, REUSE>;
-    return render_split_kernel<SVR_MIPRGB, DT, C, WIDE, REUSE>;
+static SplitFn pick_split(int mode, bool box) {
+    return box ? pick_split_mode<DT, C, WIDE, REUSE, kSmoothBox>(mode)
+               : pick_split_mode<DT, C, WIDE, REUSE, kSmoothNone>(mode);
 }
 
 // The split kernel for a volume's storage type, brick edge and addressing (REUSE as the
 // one-pass path: float32 storage at steps below a voxel).
-static SplitFn pick_split_any(int dtype, int brick, bool wide, float dt, int mode) {
+static SplitFn pick_split_any(int dtype, int brick, bool wide, float dt, int mode, bool box) {
     const bool reuse = dtype == SVR_F32 && dt < 1.0f;
 #define SVR_SPLIT_DT(C, W)                                                                 \
-    if (dtype == SVR_F16) return pick_split<SVR_F16, C, W, false>(mode);                  \
-    if (dtype == SVR_BF16) return pick_split<SVR_BF16, C, W, false>(mode);                \
-    return reuse ? pick_split<SVR_F32, C, W, true>(mode) : pick_split<SVR_F32, C, W, false>(mode)
+    if (dtype == SVR_F16) return pick_split<SVR_F16, C, W, false>(mode, box);             \
+    if (dtype == SVR_BF16) return pick_split<SVR_BF16, C, W, false>(mode, box);           \
+    return reuse ? pick_split<SVR_F32, C, W, true>(mode, box)                              \
+                 : pick_split<SVR_F32, C, W, false>(mode, box)
     if (brick == 16) {
         if (wide) { SVR_SPLIT_DT(16, true); }
         SVR_SPLIT_DT(16, false);
@@ -183,7 +192,7 @@ static bool axis_parallel(const svr_camera& cam) {
 }
 
 int render_segments(const svr_camera& cam, const VolDesc& v, const svr_params& p) {
-    if (p.mode > SVR_MIPRGB || p.ratio != 0 || p.box_arm != 0 || p.star_n != 0) return 1;
+    if (p.mode > SVR_MIPRGB || p.ratio != 0 || p.star_n != 0) return 1;
     if (axis_parallel(cam)) return 1;
     const double rays = (double)cam.width * cam.height;
     const double longest = sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz) /
@@ -277,8 +286,10 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
         hipLaunchKernelGGL(split_clear_kernel, dim3((unsigned)((npix + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, stream, reinterpret_cast<unsigned long long*>(out),
                            npix);
-        SplitFn sf = pick_split_any(v->d.dtype, v->d.brick, wide, p.dt, p.mode);
-        hipLaunchKernelGGL(sf, dim3((unsigned)(a.nblocks * nseg)), dim3(kBlock), 0, stream, a,
+        const bool box = p.box_arm > 0;
+        SplitFn sf = pick_split_any(v->d.dtype, v->d.brick, wide, p.dt, p.mode, box);
+        const size_t ring = box ? (size_t)(2 * p.box_arm + 1) * kBlock * sizeof(float) : 0;
+        hipLaunchKernelGGL(sf, dim3((unsigned)(a.nblocks * nseg)), dim3(kBlock), ring, stream, a,
                            nseg);
         const size_t lds = (size_t)(lut.n + 1) * sizeof(float4);
         RenderFn fin = p.mode == SVR_MIP0   ? split_finalize_kernel<SVR_MIP0>

@@ -45,14 +45,15 @@ def _params(mode, filt, **kw):
     return p
 
 
+@pytest.mark.parametrize("box", [0, 2])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("filt", ["none", "clip", "scale"])
 @pytest.mark.parametrize("mode", MIPS)
-def test_split_parity_with_oracle(svr, ragged, mode, filt, storage):
+def test_split_parity_with_oracle(svr, ragged, mode, filt, storage, box):
     cube, lo, hi, cam = ragged
-    print(f"[split] mode={mode} filter={filt} storage={storage}", flush=True)
+    print(f"[split] mode={mode} filter={filt} storage={storage} box={box}", flush=True)
     lut = synth.lut_heat(256)
-    params = _params(mode, filt)
+    params = _params(mode, filt, box_arm=box)
     vol = svr.svr_volume_create(to_cuda(cube), storage=storage)
     nseg = svr.svr_render_segments(vol, cam, params)
     assert nseg == 8
@@ -91,17 +92,19 @@ def test_split_mip_alpha(svr, ragged, mode, mip_alpha):
     vol.close()
 
 
+@pytest.mark.parametrize("box", [0, 3])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("mode", MIPS)
-def test_split_equals_one_pass(svr, ragged, mode, storage):
+def test_split_equals_one_pass(svr, ragged, mode, storage, box):
     """The split render and the batched one-pass render of the same view are equal bit for
     bit, sample counts included (the maximum over segment keys picks the sample the one-pass
-    '>=' picks)."""
+    '>=' picks; with box smoothing each segment's raw stream starts box_arm samples early, so
+    its means are the whole ray's)."""
     import torch
     cube, lo, hi, cam = ragged
-    print(f"[split] one-pass identity mode={mode} storage={storage}", flush=True)
+    print(f"[split] one-pass identity mode={mode} storage={storage} box={box}", flush=True)
     lut = to_cuda(synth.lut_heat(256))
-    params = _params(mode, "clip", mip_alpha=2)
+    params = _params(mode, "clip", mip_alpha=2, box_arm=box)
     vol = svr.svr_volume_create(to_cuda(cube), storage=storage)
     assert svr.svr_render_segments(vol, cam, params) > 1
     img, ns = svr.svr_render(vol, cam, lut, params, samples=True)
@@ -115,15 +118,17 @@ def test_split_equals_one_pass(svr, ragged, mode, storage):
 
 
 def test_split_segment_choice(svr, ragged):
-    """One pass for the AVIP transfer functions, the smoothing forms, small renders and
+    """One pass for the AVIP transfer functions, the in-ray Gaussian, small renders and
     parallel views along a volume axis; up to 8 segments for oblique MIP views with few rays
-    and long ones."""
+    and long ones, box smoothing included."""
     cube, lo, hi, cam = ragged
     vol = svr.svr_volume_create(to_cuda(cube))
     assert svr.svr_render_segments(vol, cam, _params("mip0", "none")) == 8
     assert svr.svr_render_segments(vol, cam, _params("miprgb", "clip")) == 8
+    assert svr.svr_render_segments(vol, cam, _params("mip1", "none", box_arm=1)) == 8
     assert svr.svr_render_segments(vol, cam, _params("avip0", "none", k=0.2)) == 1
-    assert svr.svr_render_segments(vol, cam, _params("mip0", "none", box_arm=1)) == 1
+    star = (0.375, [(1.0, 0.25), (2.0, 0.0625)])
+    assert svr.svr_render_segments(vol, cam, _params("mip0", "none", star=star)) == 1
     assert svr.svr_render_segments(vol, cam, dict(mode="mip0", dt=0.5)) == 1
     ortho = synth.ortho_axis(45, 37, 70, 90, 61, "+z").as_f32()
     assert svr.svr_render_segments(vol, ortho, _params("mip0", "none")) == 1
