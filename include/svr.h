@@ -192,7 +192,7 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
                       int32_t* samples_out, void* stream);
 
 /* Host-only: the number of segments svr_render splits each ray of this view into.  1 is one
- * pass per ray.  For the MIP transfer functions without smoothing or line ratio, oblique views
+ * pass per ray.  For the MIP transfer functions (raw or box-smoothed), oblique views
  * with few rays and many samples split each ray's samples over up to 8 workgroups, so more
  * loads are in flight (parallel views along a volume axis stay one pass: they stream the
  * bricks in order); a per-pixel 64-bit maximum of (s, k) keys then selects the same sample

@@ -44,15 +44,15 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
 using RenderFn = void (*)(RenderArgs);
 
 // ------------------------------------------------------------------ split MIP rays
-// Views with few rays (the low-density, HBM-bound regime: a quarter of a sample per voxel)
-// give one or two waves per SIMD, too few loads in flight for the memory system.  For the MIP
-// transfer functions the samples of a ray can be split into nseg segments rendered by
-// different workgroups: each segment keeps its maximum s and the index k of its last maximal
-// sample, and the per-pixel maximum of the 64-bit keys (s << 32 | k), larger s first, then
-// the later k, is Eq. MIP's '>=' over the whole ray exactly.  Sample positions are formed from the sample index (RaySource), so every
-// segment samples the points of the whole ray and the image equals the one-pass render.
-// The key lives in the first 8 bytes of the pixel's output until the finalising kernel
-// writes the fragment there.
+// Oblique views with few rays leave the SIMDs short of waves to hide the latency of their
+// gathers.  For the MIP transfer functions the samples of a ray can be split into nseg
+// segments rendered by different workgroups: each segment keeps its maximum s and the index
+// k of its last maximal sample, and the per-pixel maximum of the 64-bit keys (s << 32 | k),
+// larger s first, then the later k, is Eq. MIP's '>=' over the whole ray exactly.  Sample
+// positions are formed from the sample index (RaySource) and a box-smoothed segment starts
+// its raw stream box_arm samples early, so every segment sees the values of the whole ray
+// and the image equals the one-pass render.  The key lives in the first 8 bytes of the
+// pixel's output until the finalising kernel writes the fragment there.
 // Unsigned integers ordered as the floats they encode (-0 taken as +0): the sign bit is set
 // for non-negative values and every bit is inverted for negative ones.
 __device__ __forceinline__ uint32_t order_key(float x) {
