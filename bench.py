@@ -28,6 +28,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -71,11 +72,20 @@ def kernel_family(kernel):
     raise KeyError(kernel)
 
 
+def _code_only(text):
+    """C++ source without comments and blank space: edits to comments leave it unchanged.
+    (String and character literals in these sources hold no comment markers.)"""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash(kernel):
+    """Hash of the code (comments stripped) of the sources a kernel family is built from."""
     h = hashlib.sha256()
     for n in KERNEL_SOURCES[kernel_family(kernel)]:
-        with open(os.path.join(ROOT, "paper_1707_00442_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1707_00442_amd", "csrc", n)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
