@@ -122,7 +122,8 @@ typedef struct {
 } svr_camera;
 
 /* Colour map (Section 2.1): n RGBA float entries, entry j at s = j/(n-1), linearly
- * interpolated; 2 <= n <= SVR_MAX_LUT.  Device memory. */
+ * interpolated; 2 <= n <= SVR_MAX_LUT.  Device memory, 16-byte aligned (SVR_EINVAL
+ * otherwise). */
 typedef struct {
     const float* rgba;
     int32_t n;
@@ -182,7 +183,8 @@ typedef struct {
  * SVR_OK or SVR_EINVAL with svr_last_error() naming the offending field. */
 svr_status svr_params_validate(const svr_params* params);
 
-/* Render one image: rgba_out[height][width][4] float32 (row py = v).  A ray that misses the
+/* Render one image: rgba_out[height][width][4] float32 (row py = v), 16-byte aligned
+ * (SVR_EINVAL otherwise).  A ray that misses the
  * volume gives (0,0,0,0).  samples_out (may be NULL) receives, per pixel, the number of
  * samples the transfer function consumed (all N for MIP, up to and including the
  * terminating sample for AVIP).  vol2 is the second line cube for ratio methods (same
@@ -252,7 +254,8 @@ svr_status svr_render_train_workspace(const svr_volume* vol, const svr_camera* c
 svr_status svr_render_train(const svr_volume* vol, const svr_camera* cam, const svr_lut* tf,
                             const svr_params* params, float* rgba_out, void* workspace,
                             size_t workspace_bytes, void* stream);
-/* grad_rgba[height][width][4] = dL/dRGBA.  grad_tf[n*4] and grad_vox[nz*ny*nx] (float32,
+/* rgba_out, the workspace and grad_rgba are 16-byte aligned (SVR_EINVAL otherwise).
+ * grad_rgba[height][width][4] = dL/dRGBA.  grad_tf[n*4] and grad_vox[nz*ny*nx] (float32,
  * C-contiguous [z][y][x]; may be NULL) are ACCUMULATED with atomics: zero them first.
  * The termination index, the interval of the table and the minVal clamp are held at the
  * forward pass's values. */
@@ -266,7 +269,8 @@ svr_status svr_render_backward(const svr_volume* vol, const svr_camera* cam, con
  * a device work queue of (volume, tile) items ordered by estimated cost is drained by
  * workgroups that claim items with an atomic counter.  The launch pair (counter reset,
  * persistent kernel) is captured once into a HIP graph; svr_batch_launch replays it.  The
- * lut/params/volumes/outputs must stay alive and unchanged in shape until destroy.  Each
+ * lut/params/volumes/outputs (16-byte aligned) must stay alive and unchanged in shape until
+ * destroy.  Each
  * image equals, bit for bit, what svr_render gives for that volume and camera.  The
  * many detection sub-cubes of a survey (Section 1) motivate the form.
  * tune: 0 = the default shape (the volumes' brick edge, 16 x 16 pixel tiles, 4 workgroups

@@ -80,6 +80,7 @@ svr_status check_camera(const svr_camera* c) {
 
 svr_status check_lut(const svr_lut* l) {
     SVR_CHECK(l != nullptr && l->rgba != nullptr, "null colour table");
+    SVR_CHECK(aligned_to(l->rgba, 16), "colour table not 16-byte aligned");
     SVR_CHECK(l->n >= 2 && l->n <= SVR_MAX_LUT, "colour table size %d", l->n);
     return SVR_OK;
 }
@@ -290,6 +291,8 @@ svr_status svr_render(const svr_volume* vol, const svr_volume* vol2, const svr_c
     if ((st = check_lut(lut))) return st;
     if ((st = check_params(params, vol))) return st;
     SVR_CHECK(rgba_out != nullptr, "svr_render: null output");
+    SVR_CHECK(aligned_to(rgba_out, 16), "svr_render: output not 16-byte aligned");
+    SVR_CHECK(aligned_to(samples_out, 4), "svr_render: sample counts not 4-byte aligned");
     if (params->ratio) {
         SVR_CHECK(vol2 != nullptr, "svr_render: line-ratio methods need vol2");
         SVR_CHECK(vol2->d.nx == vol->d.nx && vol2->d.ny == vol->d.ny && vol2->d.nz == vol->d.nz,

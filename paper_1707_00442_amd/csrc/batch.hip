@@ -428,6 +428,10 @@ svr_status svr_batch_create(const svr_volume* const* vols, const svr_camera* cam
             set_error("svr_batch_create: null volume or output %d", i);
             return SVR_EINVAL;
         }
+        if (!aligned_to(rgba_outs[i], 16)) {
+            set_error("svr_batch_create: output %d not 16-byte aligned", i);
+            return SVR_EINVAL;
+        }
         if ((st = check_camera(&cams[i]))) return st;
         if ((st = check_params(params, vols[i]))) return st;
         if (vols[i]->d.dtype != vols[0]->d.dtype || vols[i]->d.brick != vols[0]->d.brick) {

@@ -125,6 +125,12 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // True when the predicate holds on any lane of the wave (the same answer on every lane).
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
+// True when p is a multiple of `bytes` (the kernels load and store 16-byte RGBA texels and
+// tables, and the split MIP renders combine 8-byte keys in the output).
+inline bool aligned_to(const void* p, size_t bytes) {
+    return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+}
+
 // Workgroup b -> tile index so that each XCD (workgroups are dealt round-robin over the
 // 8 XCDs) owns one contiguous run of tiles and its L2 sees neighbouring rays.
 __host__ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {

@@ -607,6 +607,10 @@ svr_status svr_render_train(const svr_volume* vol, const svr_camera* cam, const 
         set_error("null output or workspace");
         return SVR_EINVAL;
     }
+    if (!aligned_to(rgba_out, 16) || !aligned_to(workspace, 16)) {
+        set_error("output or workspace not 16-byte aligned");
+        return SVR_EINVAL;
+    }
     const TrainGeom g = train_geom(vol, *cam, params->dt);
     if (workspace_bytes < g.bytes) {
         set_error("workspace %zu < %zu bytes", workspace_bytes, g.bytes);
@@ -644,6 +648,11 @@ svr_status svr_render_backward(const svr_volume* vol, const svr_camera* cam, con
     }
     if (!workspace || !grad_rgba || !grad_tf) {
         set_error("null workspace, grad_rgba or grad_tf");
+        return SVR_EINVAL;
+    }
+    if (!aligned_to(workspace, 16) || !aligned_to(grad_rgba, 16) || !aligned_to(grad_tf, 4) ||
+        !aligned_to(grad_vox, 4)) {
+        set_error("workspace or grad_rgba not 16-byte aligned, or a gradient not 4-byte aligned");
         return SVR_EINVAL;
     }
     const TrainGeom g = train_geom(vol, *cam, params->dt);

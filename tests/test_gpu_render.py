@@ -562,6 +562,31 @@ def test_line_ratio_pass_other_layouts(svr, layout, dtype):
     del torch
 
 
+def test_misaligned_outputs_and_tables_are_rejected(svr):
+    """Outputs and tables the kernels access as 16-byte texels must be 16-byte aligned: a
+    pointer 4 bytes off is rejected on the host (SVR_EINVAL), before any launch."""
+    import torch
+    cube = synth.blob_cube_64(0)
+    vol = svr.svr_volume_create(to_cuda(cube))
+    cam = synth.ortho_axis(64, 64, 64, 32, 32, "+z").as_f32()
+    lut = to_cuda(synth.lut_ramp(16))
+    good = svr.svr_render(vol, cam, lut, dict(mode="mip0"))
+    buf = torch.zeros(32 * 32 * 4 + 1, device="cuda")
+    bad_out = buf[1:].view(32, 32, 4)
+    with pytest.raises(svr.SvrError):
+        svr.svr_render(vol, cam, lut, dict(mode="mip0"), out=bad_out)
+    lbuf = torch.zeros(16 * 4 + 1, device="cuda")
+    lbuf[1:] = lut.reshape(-1)
+    with pytest.raises(svr.SvrError):
+        svr.svr_render(vol, cam, lbuf[1:].view(16, 4), dict(mode="mip0"))
+    with pytest.raises(svr.SvrError):
+        svr.svr_batch_create([vol], [cam], lut, dict(mode="mip0"), outs=[bad_out])
+    svr.svr_sync()
+    assert torch.equal(svr.svr_render(vol, cam, lut, dict(mode="mip0")), good)
+    vol.close()
+    del torch
+
+
 # ----------------------------------------------------------------------------- smoothing
 @pytest.mark.parametrize("taps_name", ["binomial3", "binomial5", "paper9", "binomial13", "gauss1",
                                        "gauss3", "gauss4"])
