@@ -87,12 +87,13 @@ __global__ __launch_bounds__(kBlock) void render_split_kernel(const RenderArgs a
     const int len = (r.n + nseg - 1) / nseg;
     const int k0 = seg * len;
     const int n = max(min(len, r.n - k0), 0);
-    using Smp = Sampler<DT, C, WIDE, REUSE, true, false>;
+    constexpr bool OOB = oob_reuse<MODE, DT, WIDE, REUSE>();
+    using Smp = Sampler<DT, C, WIDE, REUSE, true, OOB>;
     const Smp smp(a.v);
     float smax = -INFINITY;
     int kmax = 0;
     float* ring = reinterpret_cast<float*>(smem) + threadIdx.x;
-    for_each_value_from<SMOOTH, drive_slots<MODE, DT>()>(smp, r, k0, n, a.p.box_arm, ring,
+    for_each_value_from<SMOOTH, drive_slots<MODE, DT, OOB>()>(smp, r, k0, n, a.p.box_arm, ring,
                                    [&](int k, float v, bool active) -> bool {
                                        const float s = F(v);
                                        if (MODE == SVR_MIP0) {

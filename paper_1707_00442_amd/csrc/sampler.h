@@ -322,11 +322,12 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
 
 // Same-cell reuse through out-of-range loads (Sampler, OOB) for float32 storage addressed
 // with 32-bit offsets: measured faster for the AVIP transfer functions (AVIP0 at 8 slots
-// 10% faster, AVIP1 at 9 slots 7%, AVIP_RGB 2%) and slower for MIP, which keeps the branch.
+// 10% faster, AVIP1 at 9 slots 7%, AVIP_RGB 2%) and for MIP0 (9-17%), slower for MIP1 and
+// MIP_RGB (5-10%), which keep the branch.
 template <int MODE, int DT, bool WIDE, bool REUSE>
 constexpr bool oob_reuse() {
     return REUSE && !WIDE && DT == SVR_F32 &&
-           (MODE == SVR_AVIP0 || MODE == SVR_AVIP1 || MODE == SVR_AVIPRGB);
+           (MODE == SVR_MIP0 || MODE == SVR_AVIP0 || MODE == SVR_AVIP1 || MODE == SVR_AVIPRGB);
 }
 
 // Fetch slots of the sample loop per transfer function and storage type (measured on the
