@@ -241,7 +241,12 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
     // Alg. AVIP0 / AVIP1 / AVIP_RGB: front-to-back compositing, stop after alpha > ert.
     const float kw = a.p.k, minv = a.p.min_val, ert = a.p.ert;
     const bool ofl = a.p.opacity_from_lut != 0;
+    // normalised location of sample k per axis, loc = (p0 + k step + 0.5) / n, formed as one
+    // clamped FMA from per-ray terms (within a few float32 roundings of the direct form)
     const float inx = 1.0f / (float)a.v.nx, iny = 1.0f / (float)a.v.ny, inz = 1.0f / (float)a.v.nz;
+    const float lbx = (r.p0[0] + 0.5f) * inx, lsx = r.step[0] * inx;
+    const float lby = (r.p0[1] + 0.5f) * iny, lsy = r.step[1] * iny;
+    const float lbz = (r.p0[2] + 0.5f) * inz, lsz = r.step[2] * inz;
     Rgba t = {0.0f, 0.0f, 0.0f, 0.0f};
     int cnt = 0;
     feed.run([&](int k, float v, bool active) -> bool {
@@ -253,14 +258,14 @@ __device__ __forceinline__ void march_tf(const RenderArgs& a, const float4* s_lu
             cr = c.x; cg = c.y; cb = c.z;
             op = ofl ? c.w : s;
         } else {
-            const float lz = sat((fmaf(kf, r.step[2], r.p0[2]) + 0.5f) * inz);
+            const float lz = sat(fmaf(kf, lsz, lbz));
             if (MODE == SVR_AVIP1) {
                 const float4 c = table(s_lut, n_lut, lz);
                 cr = c.x; cg = c.y; cb = c.z;
             } else {
                 cr = lz;
-                cg = sat((fmaf(kf, r.step[1], r.p0[1]) + 0.5f) * iny);
-                cb = sat((fmaf(kf, r.step[0], r.p0[0]) + 0.5f) * inx);
+                cg = sat(fmaf(kf, lsy, lby));
+                cb = sat(fmaf(kf, lsx, lbx));
             }
             op = ofl ? table(s_lut, n_lut, s).w : s;
         }
