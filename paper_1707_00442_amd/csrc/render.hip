@@ -53,6 +53,7 @@ using RenderFn = void (*)(RenderArgs);
 // its raw stream box_arm samples early, so every segment sees the values of the whole ray
 // and the image equals the one-pass render.  The key lives in the first 8 bytes of the
 // pixel's output until the finalising kernel writes the fragment there.
+
 // Unsigned integers ordered as the floats they encode (-0 taken as +0): the sign bit is set
 // for non-negative values and every bit is inverted for negative ones.
 __device__ __forceinline__ uint32_t order_key(float x) {
