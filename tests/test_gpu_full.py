@@ -341,9 +341,10 @@ def test_render_volume_beyond_4gib(svr):
     cam = synth.rotation_views(nx, ny, nz, 960, 540)[4].as_f32()
     lut_np = synth.lut_heat(256)
     lut = to_cuda(lut_np)
-    for mode in MODES:
-        p = dict(mode=mode, k=0.1)
-        # the MIP renders of this 960 x 540 view split each ray in two (64-bit addressing)
+    cases = [dict(mode=m, k=0.1) for m in MODES] + [dict(mode="mip1", box_arm=2)]
+    for p in cases:
+        mode = p["mode"]
+        # the MIP renders of this 960 x 540 view split each ray (64-bit addressing)
         assert (svr.svr_render_segments(vol, cam, p) > 1) == mode.startswith("mip")
         img, ns = svr.svr_render(vol, cam, lut, p, clim_lo=lo, clim_hi=hi, samples=True)
         svr.svr_sync()
