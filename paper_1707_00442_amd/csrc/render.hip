@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void render_split_kernel(const RenderArgs a
     const int len = (r.n + nseg - 1) / nseg;
     const int k0 = seg * len;
     const int n = max(min(len, r.n - k0), 0);
-    constexpr bool OOB = oob_reuse<MODE, DT, WIDE, REUSE>();
+    constexpr bool OOB = oob_reuse_split<MODE, DT, WIDE, REUSE>();
     using Smp = Sampler<DT, C, WIDE, REUSE, true, OOB>;
     const Smp smp(a.v);
     float smax = -INFINITY;

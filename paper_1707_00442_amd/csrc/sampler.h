@@ -322,12 +322,19 @@ __device__ __forceinline__ void drive(Src src, int n, Body&& body) {
 
 // Same-cell reuse through out-of-range loads (Sampler, OOB) for float32 storage addressed
 // with 32-bit offsets: measured faster for the AVIP transfer functions (AVIP0 at 8 slots
-// 10% faster, AVIP1 at 9 slots 7%, AVIP_RGB 2%) and for MIP0 (9-17%), slower for MIP1 and
-// MIP_RGB (5-10%), which keep the branch.
+// 10% faster, AVIP1 at 9 slots 7%, AVIP_RGB 2%), slower for MIP1 and MIP_RGB (5-10%).
+// MIP0 gains on large volumes (the split renders use it, below) but lost 20% on a
+// cache-resident 64^3 cube, where every load costs texture-path time and none waits on HBM.
 template <int MODE, int DT, bool WIDE, bool REUSE>
 constexpr bool oob_reuse() {
     return REUSE && !WIDE && DT == SVR_F32 &&
-           (MODE == SVR_MIP0 || MODE == SVR_AVIP0 || MODE == SVR_AVIP1 || MODE == SVR_AVIPRGB);
+           (MODE == SVR_AVIP0 || MODE == SVR_AVIP1 || MODE == SVR_AVIPRGB);
+}
+// The split MIP renders (large oblique views): MIP0 takes the out-of-range loads too.
+template <int MODE, int DT, bool WIDE, bool REUSE>
+constexpr bool oob_reuse_split() {
+    return oob_reuse<MODE, DT, WIDE, REUSE>() ||
+           (REUSE && !WIDE && DT == SVR_F32 && MODE == SVR_MIP0);
 }
 
 // Fetch slots of the sample loop per transfer function and storage type (measured on the
