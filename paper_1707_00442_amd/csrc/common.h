@@ -86,6 +86,19 @@ inline VolDesc make_voldesc(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, i
     return d;
 }
 
+// Streaming accesses for data a kernel reads or writes once: the non-temporal hint keeps them
+// from displacing cached lines that other workgroups still use.  Measured: moment-map reads
+// 7% faster, smoothing writes 1-2%; line-ratio reads and stores slower on small windows that
+// later launches read again from the caches (kept plain), upload stores unchanged.
+template <class T>
+__device__ __forceinline__ T load_nt(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void store_nt(T v, T* p) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // Element loaders: stored type -> float32.
 template <int DT> struct Elem;
 template <> struct Elem<SVR_F32> {

@@ -47,7 +47,10 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const typename Elem<DT>
     for (; z + kMomAhead <= z1; z += kMomAhead) {
         float v[kMomAhead];
 #pragma unroll
-        for (int k = 0; k < kMomAhead; ++k) v[k] = Elem<DT>::get(col + (int64_t)(z + k) * sz, 0);
+        for (int k = 0; k < kMomAhead; ++k) {
+            const typename Elem<DT>::T e = load_nt(col + (int64_t)(z + k) * sz);
+            v[k] = Elem<DT>::get(&e, 0);
+        }
 #pragma unroll
         for (int k = 0; k < kMomAhead; ++k) acc.add(v[k], z + k, lo, hi);
     }

@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void smooth_fused_kernel(
                 for (int q = 0; q < kFzRy; ++q) {
                     const int gy = y0 + yg + q;
                     if (yg + q < TY && gy < ny)
-                        out[(int64_t)zo * plane + (int64_t)gy * nx + gxo] = Elem<DT_OUT>::put(acc[q]);
+                        store_nt(Elem<DT_OUT>::put(acc[q]),
+                                 out + (int64_t)zo * plane + (int64_t)gy * nx + gxo);
                 }
             }
         }
