@@ -89,7 +89,8 @@ inline VolDesc make_voldesc(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, i
 // Streaming accesses for data a kernel reads or writes once: the non-temporal hint keeps them
 // from displacing cached lines that other workgroups still use.  Measured: moment-map reads
 // 7% faster, smoothing writes 1-2%; line-ratio reads and stores slower on small windows that
-// later launches read again from the caches (kept plain), upload stores unchanged.
+// later launches read again from the caches (kept plain), upload stores unchanged and upload
+// reads 13% slower (neighbouring brick groups re-read each slab's halo rows from the caches).
 template <class T>
 __device__ __forceinline__ T load_nt(const T* p) {
     return __builtin_nontemporal_load(p);
