@@ -90,7 +90,8 @@ inline VolDesc make_voldesc(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, i
 // from displacing cached lines that other workgroups still use.  Measured: moment-map reads
 // 7% faster, smoothing writes 1-2%; line-ratio reads and stores slower on small windows that
 // later launches read again from the caches (kept plain), upload stores unchanged and upload
-// reads 13% slower (neighbouring brick groups re-read each slab's halo rows from the caches).
+// reads 13% slower (neighbouring brick groups re-read each slab's halo rows from the caches);
+// the ray-march's corner loads 1.7-3x slower (neighbouring rays share cached cells).
 template <class T>
 __device__ __forceinline__ T load_nt(const T* p) {
     return __builtin_nontemporal_load(p);
