@@ -695,6 +695,22 @@ def run_forms(torch, svr, synth, cube, lo, hi, views, lut, params, kernels, args
             gbps=nb / (ms * 1e-3) / 1e9, hbm_frac=nb / (ms * 1e-3) / PEAK_HBM,
             stored_bytes=v.nbytes, stored_gbps=v.nbytes / (ms * 1e-3) / 1e9)
         v.close()
+    # split MIP rays: an oblique view with few rays (256 x 256, rotation view 3, dt 0.5), each ray
+    # rendered in segments on several workgroups; the batched kernel renders the same view in
+    # one pass (its own tuning: context, not an A/B of the split alone)
+    cs = synth.rotation_views(512, 512, 1024, 256, 256)[3].as_f32()
+    r = {}
+    for m in ("mip0", "mip1"):
+        pm = params[m]
+        _, ns = svr.svr_render(vol32, cs, lut, pm, samples=True)
+        n = int(ns.sum().item())
+        ms = _time(torch, lambda: svr.svr_render(vol32, cs, lut, pm), 10)
+        b = svr.svr_batch_create([vol32], [cs], lut, pm, tune=0)
+        ms_b = _time(torch, b.launch, 10)
+        b.close()
+        r[m] = dict(ms=ms, segments=svr.svr_render_segments(vol32, cs, pm),
+                    samples_per_s=n / (ms * 1e-3), batched_one_pass_ms=ms_b)
+    forms["small_oblique_view_split"] = r
     # the paper's in-ray 9-tap Gaussian (13 trilinear fetches per sample), view 0
     star9 = (0.2270270270, [(1.3846153846, 0.3162162162), (3.2307692308, 0.0702702703)])
     r = {}
