@@ -258,6 +258,24 @@ static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int smooth, 
                 : pick_dt<8, false>(dtype, reuse, smooth, mode, ratio);
 }
 
+// Occupancy cap.  A launch given more than a third of the CU's 160 KiB of LDS runs at most
+// two 256-lane workgroups (two waves per SIMD) per CU.  Two kernels run faster so than at
+// the three waves their registers allow, with images unchanged: the plain AVIP_RGB march
+// (1920x1080 views of the 512x512x1024 cube, dt 0.5: 2.80 -> 2.63 ms, and the L2 misses per
+// frame 3.22 -> 2.92 GB; 16-bit storage and dt 1 11% faster) and the float32 split MIP0
+// march (2.34 -> 2.30 ms, 3.18 -> 2.90 GB).  At two waves,
+// deeper pipelines (7 or 8 fetch slots for AVIP_RGB, 8 or 10 for MIP0) were slower again
+// (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) both were 3-6% slower
+// than at three: the gathers in flight per CU, not the waves to hide their latency, set
+// the speed.
+// The other kernels are not capped: the box-smoothed marches, 16-bit MIP and AVIP0 and the
+// dt >= 1 views of uniform cubes ran 5-29% slower with the cap.
+constexpr size_t kTwoGroupsLds = 56 * 1024;
+
+static size_t capped_lds(size_t need, bool cap) {
+    return cap && need < kTwoGroupsLds ? kTwoGroupsLds : need;
+}
+
 size_t render_lds_bytes(int lut_n, int box_arm, int ratio) {
     size_t b = (size_t)(lut_n + 1) * sizeof(float4);
     if (ratio == 0 && box_arm > 0) b += (size_t)(2 * box_arm + 1) * kBlock * sizeof(float);
@@ -291,8 +309,9 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
         const bool box = p.box_arm > 0;
         SplitFn sf = pick_split_any(v->d.dtype, v->d.brick, wide, p.dt, p.mode, box);
         const size_t ring = box ? (size_t)(2 * p.box_arm + 1) * kBlock * sizeof(float) : 0;
-        hipLaunchKernelGGL(sf, dim3((unsigned)(a.nblocks * nseg)), dim3(kBlock), ring, stream, a,
-                           nseg);
+        const bool cap = !box && p.mode == SVR_MIP0 && v->d.dtype == SVR_F32;
+        hipLaunchKernelGGL(sf, dim3((unsigned)(a.nblocks * nseg)), dim3(kBlock),
+                           capped_lds(ring, cap), stream, a, nseg);
         const size_t lds = (size_t)(lut.n + 1) * sizeof(float4);
         RenderFn fin = p.mode == SVR_MIP0   ? split_finalize_kernel<SVR_MIP0>
                        : p.mode == SVR_MIP1 ? split_finalize_kernel<SVR_MIP1>
@@ -301,7 +320,8 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
         return hip_fail(hipGetLastError(), "render launch (split rays)");
     }
     RenderFn fn = pick_any(v->d.dtype, v->d.brick, wide, p.dt, smooth, p.mode, p.ratio);
-    const size_t lds = render_lds_bytes(lut.n, p.box_arm, p.ratio);
+    const bool cap = p.mode == SVR_AVIPRGB && smooth == kSmoothNone && p.ratio == 0;
+    const size_t lds = capped_lds(render_lds_bytes(lut.n, p.box_arm, p.ratio), cap);
     hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(kBlock), lds, stream, a);
     return hip_fail(hipGetLastError(), "render launch");
 }
