@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void render_split_kernel(const RenderArgs a
     const int len = (r.n + nseg - 1) / nseg;
     const int k0 = seg * len;
     const int n = max(min(len, r.n - k0), 0);
-    constexpr bool OOB = oob_reuse_split<MODE, DT, WIDE, REUSE>();
+    constexpr bool OOB = oob_reuse_split<MODE, DT, WIDE, REUSE, SMOOTH == kSmoothBox>();
     using Smp = Sampler<DT, C, WIDE, REUSE, true, OOB>;
     const Smp smp(a.v);
     float smax = -INFINITY;
@@ -259,17 +259,19 @@ static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int smooth, 
 }
 
 // Occupancy cap.  A launch given more than a third of the CU's 160 KiB of LDS runs at most
-// two 256-lane workgroups (two waves per SIMD) per CU.  Two kernels run faster so than at
-// the three waves their registers allow, with images unchanged: the plain AVIP_RGB march
-// (1920x1080 views of the 512x512x1024 cube, dt 0.5: 2.80 -> 2.63 ms, and the L2 misses per
-// frame 3.22 -> 2.92 GB; 16-bit storage and dt 1 11% faster) and the float32 split MIP0
-// march (2.34 -> 2.30 ms, 3.18 -> 2.90 GB).  At two waves,
-// deeper pipelines (7 or 8 fetch slots for AVIP_RGB, 8 or 10 for MIP0) were slower again
-// (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) both were 3-6% slower
-// than at three: the gathers in flight per CU, not the waves to hide their latency, set
-// the speed.
-// The other kernels are not capped: the box-smoothed marches, 16-bit MIP and AVIP0 and the
-// dt >= 1 views of uniform cubes ran 5-29% slower with the cap.
+// two 256-lane workgroups (two waves per SIMD) per CU.  These kernels run faster so than at
+// the three or four waves their registers allow, with images unchanged:
+// - the plain AVIP_RGB march (1920x1080 views of the 512x512x1024 cube, dt 0.5: 2.80 -> 2.63
+//   ms, and the L2 misses per frame 3.22 -> 2.92 GB; 16-bit storage and dt 1 11% faster);
+// - the float32 split MIP marches with the out-of-range reuse loads (dt < 1): MIP0 2.34 ->
+//   2.30 ms (3.18 -> 2.90 GB); MIP1 and MIP_RGB (128 VGPRs) 2.57 ms with the reuse branch,
+//   2.76 ms with the reuse loads at four waves, 2.65 at three and 2.51 at two.
+// At two waves, deeper pipelines (7 or 8 fetch slots for AVIP_RGB, 8 or 10 for MIP0) were
+// slower again (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) AVIP_RGB and
+// MIP0 were 3-6% slower than at three: the gathers in flight per CU, not the waves to hide
+// their latency, set the speed.  The other kernels are not capped: the box-smoothed
+// marches, 16-bit MIP and AVIP0 and the dt >= 1 views of uniform cubes ran 5-29% slower
+// with the cap.
 constexpr size_t kTwoGroupsLds = 56 * 1024;
 
 static size_t capped_lds(size_t need, bool cap) {
@@ -309,7 +311,7 @@ svr_status launch_render(const svr_volume* v, const svr_volume* v2, const svr_ca
         const bool box = p.box_arm > 0;
         SplitFn sf = pick_split_any(v->d.dtype, v->d.brick, wide, p.dt, p.mode, box);
         const size_t ring = box ? (size_t)(2 * p.box_arm + 1) * kBlock * sizeof(float) : 0;
-        const bool cap = !box && p.mode == SVR_MIP0 && v->d.dtype == SVR_F32;
+        const bool cap = !box && v->d.dtype == SVR_F32 && p.dt < 1.0f && !wide;
         hipLaunchKernelGGL(sf, dim3((unsigned)(a.nblocks * nseg)), dim3(kBlock),
                            capped_lds(ring, cap), stream, a, nseg);
         const size_t lds = (size_t)(lut.n + 1) * sizeof(float4);

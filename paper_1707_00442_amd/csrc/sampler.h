@@ -330,11 +330,15 @@ constexpr bool oob_reuse() {
     return REUSE && !WIDE && DT == SVR_F32 &&
            (MODE == SVR_AVIP0 || MODE == SVR_AVIP1 || MODE == SVR_AVIPRGB);
 }
-// The split MIP renders (large oblique views): MIP0 takes the out-of-range loads too.
-template <int MODE, int DT, bool WIDE, bool REUSE>
+// The split MIP renders (large oblique views) take the out-of-range loads too: MIP0 always,
+// MIP1 and MIP_RGB without box smoothing, where their launches are capped at two workgroups
+// per CU (uncapped, at 128 VGPRs, they ran four waves per SIMD and were slower than with
+// the reuse branch).
+template <int MODE, int DT, bool WIDE, bool REUSE, bool BOX>
 constexpr bool oob_reuse_split() {
     return oob_reuse<MODE, DT, WIDE, REUSE>() ||
-           (REUSE && !WIDE && DT == SVR_F32 && MODE == SVR_MIP0);
+           (REUSE && !WIDE && DT == SVR_F32 &&
+            (MODE == SVR_MIP0 || (MODE <= SVR_MIPRGB && !BOX)));
 }
 
 // Fetch slots of the sample loop per transfer function and storage type (measured on the
