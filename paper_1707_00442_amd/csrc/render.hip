@@ -264,8 +264,9 @@ static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int smooth, 
 // - the plain AVIP_RGB march (1920x1080 views of the 512x512x1024 cube, dt 0.5: 2.80 -> 2.63
 //   ms, and the L2 misses per frame 3.22 -> 2.92 GB; 16-bit storage and dt 1 11% faster);
 // - the float32 split MIP marches with the out-of-range reuse loads (dt < 1): MIP0 2.34 ->
-//   2.30 ms (3.18 -> 2.90 GB); MIP1 and MIP_RGB (128 VGPRs) 2.57 ms with the reuse branch,
-//   2.76 ms with the reuse loads at four waves, 2.65 at three and 2.51 at two.
+//   2.30 ms (3.18 -> 2.90 GB); MIP1 and MIP_RGB 2.57 ms with the reuse branch, with the reuse
+//   loads at six fetch slots (128 VGPRs) 2.76 ms at four waves, 2.65 at three and 2.51 at
+//   two, and 2.41 ms at eight slots (163 VGPRs) and two waves.
 // At two waves, deeper pipelines (7 or 8 fetch slots for AVIP_RGB, 8 or 10 for MIP0) were
 // slower again (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) AVIP_RGB and
 // MIP0 were 3-6% slower than at three: the gathers in flight per CU, not the waves to hide

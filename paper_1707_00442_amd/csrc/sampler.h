@@ -347,6 +347,9 @@ constexpr bool oob_reuse_split() {
 // packed 16-bit slots are half the size of float32 ones and go deeper).
 template <int MODE, int DT, bool OOB = false>
 constexpr int drive_slots() {
+    // split MIP1 / MIP_RGB with the reuse loads, two waves per SIMD: 8 slots 2.41 ms, 6 2.51,
+    // 5 2.61, 10 2.44, 12 2.42
+    if ((MODE == SVR_MIP1 || MODE == SVR_MIPRGB) && DT == SVR_F32 && OOB) return 8;
     if (MODE == SVR_MIP0 || MODE == SVR_MIP1 || MODE == SVR_MIPRGB) return DT == SVR_F32 ? 6 : 8;
     if (MODE == SVR_AVIPRGB) return DT == SVR_F32 ? 5 : 7;
     if (MODE == SVR_AVIP0) return OOB ? 8 : 6;
