@@ -271,8 +271,8 @@ static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int smooth, 
 // slower again (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) AVIP_RGB and
 // MIP0 were 3-6% slower than at three: the gathers in flight per CU, not the waves to hide
 // their latency, set the speed.  The other kernels are not capped: the box-smoothed
-// marches, 16-bit MIP and AVIP0 and the dt >= 1 views of uniform cubes ran 5-29% slower
-// with the cap.
+// marches, 16-bit MIP and AVIP0, the dt >= 1 views of uniform cubes and the line-ratio
+// methods ran 5-29% slower with the cap.
 constexpr size_t kTwoGroupsLds = 56 * 1024;
 
 static size_t capped_lds(size_t need, bool cap) {
