@@ -267,8 +267,8 @@ static RenderFn pick_any(int dtype, int brick, bool wide, float dt, int smooth, 
 //   2.30 ms (3.18 -> 2.90 GB); MIP1 and MIP_RGB 2.57 ms with the reuse branch, with the reuse
 //   loads at six fetch slots (128 VGPRs) 2.76 ms at four waves, 2.65 at three and 2.51 at
 //   two, and 2.41 ms at eight slots (163 VGPRs) and two waves.
-// At two waves, deeper pipelines (7 or 8 fetch slots for AVIP_RGB, 8 or 10 for MIP0) were
-// slower again (2.74-2.75 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) AVIP_RGB and
+// At two waves, deeper pipelines (6 to 8 fetch slots for AVIP_RGB, 7 to 10 for MIP0) were
+// slower again (2.74-2.76 / 2.39-2.47 ms), and at four waves (124 / 127 VGPRs) AVIP_RGB and
 // MIP0 were 3-6% slower than at three: the gathers in flight per CU, not the waves to hide
 // their latency, set the speed.  The other kernels are not capped: the box-smoothed
 // marches, 16-bit MIP and AVIP0, the dt >= 1 views of uniform cubes and the line-ratio
